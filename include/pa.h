@@ -1,0 +1,189 @@
+/*
+ * pa.h -- C ABI of libpa: population annealing (PA) of the 2D ferromagnetic
+ * Ising model on L x L periodic lattices, run on one MI355X (gfx950).
+ *
+ * Method: Barash, Weigel, Borovsky, Janke, Shchur, "GPU accelerated population
+ * annealing algorithm" (arXiv:1703.03676).  One PA run holds a population of
+ * R_i replicas at inverse temperature beta_i.  Per temperature step the caller
+ *   1. picks beta_{i+1} (fixed step, or pa_adapt_beta: Sec. 2.3),
+ *   2. calls pa_resample (Sec. 2.1 step 2, Eqs. (Q) and (resampling factors)),
+ *   3. calls pa_sweep(theta) (Sec. 2.1 step 3; checkerboard Metropolis, Sec. 3),
+ *   4. calls pa_observables (Sec. 2.1 step 4, Eqs. (observables), (free
+ *      energy), (entropy)),
+ * and at the end may call pa_reweight (Sec. 2.4, multi-histogram Eq.).
+ *
+ * Conventions shared by every call:
+ *   - Every call returns pa_status; 0 (PA_OK) is success.  No exception or
+ *     abort crosses the ABI.  After PA_EHIP the run is unusable and later calls
+ *     return PA_ESTATE; pa_free is always allowed.
+ *   - Device memory belongs to the caller: pa_init receives one device buffer of
+ *     at least pa_workspace_bytes(p) bytes that must outlive the run.  The
+ *     library allocates no device memory of its own.
+ *   - The HIP stream passed to pa_init is borrowed; all device work of the run
+ *     is enqueued on it.  Calls that return host values (pa_resample's info,
+ *     pa_adapt_beta, pa_observables, pa_reweight, the download hooks)
+ *     synchronise that stream before returning.
+ *   - Spin convention: +1 / -1; J = 1, h = 0; E = -sum over the 2N bonds;
+ *     M = sum of spins.  Energies are multiples of 4 in [-2N, 2N].
+ *   - Random numbers: Philox4x32-10 keyed by (seed_lo32, seed_hi32 ^ run_id),
+ *     with counters derived from (replica slot, sweep number, colour, site) for
+ *     the sweep, (parent slot, step) for resampling and (replica, site) for the
+ *     initial state.  Results are therefore bit-reproducible for a given seed
+ *     and schedule, independent of launch shapes.
+ */
+#ifndef PA_H
+#define PA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PA_OK = 0,
+    PA_EINVAL = -1,     /* invalid argument (validated on the host before any launch) */
+    PA_ENOMEM = -2,     /* workspace too small / host allocation failed */
+    PA_ECAPACITY = -3,  /* resampled population would exceed the capacity; state unchanged */
+    PA_EHIP = -4,       /* a HIP runtime call failed; see pa_last_error */
+    PA_ESTATE = -5,     /* run unusable (after PA_EHIP) or call out of order */
+    PA_EEXTINCT = -6    /* resampling would leave no replica; state unchanged */
+} pa_status;
+
+typedef enum {
+    PA_SPIN_INT8 = 0,   /* one signed byte (+1 / -1) per spin, row-major (single-spin coding) */
+    PA_SPIN_BITS = 1    /* one bit per spin, per-colour 32-site words (multi-spin coding) */
+} pa_layout;
+
+enum {
+    PA_FLAG_MHR = 1     /* accumulate the per-energy histograms used by pa_reweight */
+};
+
+typedef struct {
+    int32_t L;          /* lattice edge; this build runs L in {16, 32, 64, 128, 256} */
+    int32_t R;          /* target population size R (Sec. 2.1), >= 1 */
+    int32_t capacity;   /* maximum population; 0 selects R + ceil(10 sqrt(R)) + 64 */
+    int32_t layout;     /* pa_layout of the spin store */
+    uint64_t seed;      /* Philox key material */
+    uint32_t run_id;    /* xored into the key's high word: independent runs */
+    uint32_t flags;     /* PA_FLAG_* */
+} pa_params;
+
+/* Population averages at the current beta: the ten output columns the paper
+ * lists for each temperature (Sec. 3, program output), then the exact integer
+ * sums they come from.  sumM4 is a 128-bit unsigned value split in two words. */
+typedef struct {
+    double beta, e, C, abs_m, m2, m4, betaF_per_N, S_per_N, lnQ;
+    int64_t R;
+    int64_t sumE, sumE2, sumAbsM, sumM2;
+    uint64_t sumM4_lo, sumM4_hi;
+} pa_obs;
+
+typedef struct {
+    double lnQ;         /* ln Q_i of Eq. (Q) */
+    int64_t R_new;      /* R_i = sum of copy counts */
+    int32_t E_min;      /* smallest energy in the parent population (weight shift) */
+} pa_resample_info;
+
+typedef struct {
+    int64_t R;          /* current population size R_i */
+    int32_t step;       /* number of resampling steps done (i) */
+    uint64_t sweeps;    /* sweeps done in this run (keys the sweep random stream) */
+    double beta;        /* current beta_i */
+    double lnZ;         /* ln Z(beta_i) estimate, Eq. (free energy) */
+} pa_state_info;
+
+typedef struct pa_run pa_run;  /* opaque host handle */
+
+/* Bytes of device workspace a run with these parameters needs; 0 if the
+ * parameters are invalid.  Pure host function. */
+size_t pa_workspace_bytes(const pa_params* p);
+
+/* Start a run at beta_0 = 0 (Sec. 2.1 step 1): R independent uniformly random
+ * configurations; ln Z_0 = N ln 2.  `d_workspace` is a device pointer to at
+ * least `bytes` bytes, 256-byte aligned; `hip_stream` is a hipStream_t (NULL:
+ * the null stream).  On success *out receives the handle.
+ * Errors: PA_EINVAL (L not supported, R < 1, capacity < R, bad layout, NULL
+ * pointers), PA_ENOMEM (bytes too small), PA_EHIP. */
+pa_status pa_init(const pa_params* p, void* d_workspace, size_t bytes, void* hip_stream, pa_run** out);
+
+/* nsweeps checkerboard Metropolis sweeps of every replica at the current beta
+ * (Sec. 2.1 step 3; Sec. 3 spin updates).  One sweep updates colour (x+y) even,
+ * then odd.  A spin with local field h flips if k = s h <= 0, else with
+ * probability exp(-2 beta k), decided against an integer threshold
+ * ceil(2^32 exp(-2 beta k)).  Updates E_j and M_j.  Asynchronous.
+ * Errors: PA_EINVAL (nsweeps < 0), PA_ESTATE, PA_EHIP. */
+pa_status pa_sweep(pa_run* r, int32_t nsweeps);
+
+/* Resample the population from beta_i to beta_next >= beta_i (Sec. 2.1 step 2):
+ * reweight by exp(-(beta_next - beta_i) E), Q from Eq. (Q), copy counts by
+ * Eq. (resampling factors) with one uniform per parent, prefix-sum compaction,
+ * replica copy.  Parents keep their order; copies of one parent are adjacent.
+ * Updates ln Z += ln Q.  `out` may be NULL.
+ * Errors: PA_EINVAL (beta_next < beta_i or not finite), PA_ECAPACITY and
+ * PA_EEXTINCT (R_i would exceed the capacity / be 0; state left at step i),
+ * PA_ESTATE, PA_EHIP. */
+pa_status pa_resample(pa_run* r, double beta_next, pa_resample_info* out);
+
+/* Histogram-overlap adaptive step (Sec. 2.3): returns in *beta_next the
+ * largest beta' <= beta_f (found by bisection, 50 halvings) with
+ * alpha(beta_i, beta') >= alpha_star, or beta_f if alpha(beta_f) >= alpha_star.
+ * alpha_at_next may be NULL.  Does not change the run.
+ * Errors: PA_EINVAL (alpha_star not in (0,1), beta_f < beta_i, or no step above
+ * beta_i reaches alpha_star), PA_ESTATE, PA_EHIP. */
+pa_status pa_adapt_beta(pa_run* r, double alpha_star, double beta_f, double* beta_next, double* alpha_at_next);
+
+/* Overlap alpha(beta_i, beta_prime) of Sec. 2.3 for the current population. */
+pa_status pa_alpha(pa_run* r, double beta_prime, double* alpha);
+
+/* Population averages at the current beta (Eq. (observables)), -beta F/N from
+ * Eq. (free energy), S/N from Eq. (entropy), and the exact integer sums.  With
+ * PA_FLAG_MHR each call also adds the population's energy histogram (and
+ * per-energy magnetisation sums) to the reweighting accumulators.
+ * Errors: PA_EINVAL (out NULL), PA_ESTATE, PA_EHIP. */
+pa_status pa_observables(pa_run* r, pa_obs* out);
+
+/* Multi-histogram reweighting (Sec. 2.4): the density of states from all
+ * measurements taken so far, then e, C, <|m|>, <m^2>, <m^4>, beta F/N and S/N
+ * at each of the nb inverse temperatures betas[0..nb).  out[k].R and
+ * out[k].lnQ and the integer sums are 0.  Requires PA_FLAG_MHR.
+ * Errors: PA_EINVAL (flag not set, nb < 0, NULL pointers, no measurement),
+ * PA_ESTATE, PA_EHIP. */
+pa_status pa_reweight(pa_run* r, const double* betas, int32_t nb, pa_obs* out);
+
+/* Current counters of the run (host values, no synchronisation). */
+pa_status pa_state(const pa_run* r, pa_state_info* out);
+
+/* Release the host handle (the caller frees the workspace).  NULL is allowed. */
+pa_status pa_free(pa_run* r);
+
+/* Static description of a status code. */
+const char* pa_strerror(pa_status s);
+
+/* Text of the last error of this run ("" if none). */
+const char* pa_last_error(const pa_run* r);
+
+/* ---- Test hooks: step-wise comparison with a reference implementation. ---- */
+
+/* Copy the population to host memory: spins as int8 +-1, row-major,
+ * [R_i][L][L] (converted from the run's layout); E and M as int32 [R_i].
+ * Any pointer may be NULL. */
+pa_status pa_download_population(pa_run* r, int8_t* spins, int32_t* E, int32_t* M);
+
+/* Replace the population by R_cur host configurations (int8 +-1, row-major)
+ * and set the counters that key the random streams.  E and M are recomputed on
+ * the device from the spins.  Errors: PA_EINVAL (R_cur out of [1, capacity],
+ * spin values not +-1), PA_ESTATE, PA_EHIP. */
+pa_status pa_upload_population(pa_run* r, int32_t R_cur, const int8_t* spins, int32_t step,
+                               uint64_t sweeps, double beta, double lnZ);
+
+/* Copy counts of the last resampling step, one per parent: *n receives the
+ * number of parents; counts must hold capacity entries. */
+pa_status pa_download_counts(pa_run* r, uint32_t* counts, int32_t* n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PA_H */

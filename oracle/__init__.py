@@ -86,6 +86,7 @@ def load(path):
         "orc_set_population": (i32, [vp, i32, vp, i32, u64, dbl, dbl]),
         "orc_recount": (None, [vp, i32, P(ctypes.c_int32), P(ctypes.c_int32)]),
         "orc_tables": (dbl, [i32, i32, i32, vp, dbl, vp, vp]),
+        "orc_set_slots": (None, [vp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -154,8 +155,10 @@ class Run:
         lnq = ctypes.c_double()
         emin = ctypes.c_int32()
         rn = self.lib.orc_resample(self.h, float(beta_next), ctypes.byref(lnq), ctypes.byref(emin))
-        if rn < 0:
+        if rn == -1:
             raise OverflowError("population exceeds capacity")
+        if rn < 0:
+            raise ArithmeticError("no replica would survive")
         return {"R_new": rn, "lnQ": lnq.value, "E_min": emin.value}
 
     def alpha(self, beta_prime):
@@ -220,6 +223,15 @@ class Run:
         st = self.lib.orc_set_population(self.h, n, _ptr(spins), int(step), int(sweeps), float(beta), float(lnZ))
         if st != 0:
             raise ValueError("population does not fit")
+
+    def set_slots(self, slots):
+        """Random-stream slot of each replica for later sweeps (None: identity)."""
+        if slots is None:
+            self.lib.orc_set_slots(self.h, None)
+        else:
+            self._slots = np.ascontiguousarray(slots, dtype=np.int32)
+            assert len(self._slots) == self.population
+            self.lib.orc_set_slots(self.h, _ptr(self._slots))
 
     def recount(self, j):
         e, m = ctypes.c_int32(), ctypes.c_int32()

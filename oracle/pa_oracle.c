@@ -126,6 +126,8 @@ typedef struct {
     int32_t *E2, *M2;
     uint32_t *counts;   /* copy counts of the last resampling (per parent) */
     int counts_n;
+    int32_t *slot;      /* optional: random-stream slot of each replica in a sweep
+                           (NULL: replica j uses slot j); for sampled checks */
     /* multi-histogram accumulators, one bin per energy level */
     int64_t *H, *SA, *SM2;
     unsigned __int128 *SM4;
@@ -192,7 +194,7 @@ void orc_free(orc_run *r)
     if (!r) return;
     free(r->spin); free(r->spin2); free(r->E); free(r->M); free(r->E2); free(r->M2);
     free(r->counts); free(r->H); free(r->SA); free(r->SM2); free(r->SM4);
-    free(r->m_beta); free(r->m_lnZ); free(r->m_R);
+    free(r->m_beta); free(r->m_lnZ); free(r->m_R); free(r->slot);
     free(r);
 }
 
@@ -269,9 +271,10 @@ void orc_sweep(orc_run *r, int nsweeps)
         for (int c = 0; c < 2; ++c)
             for (int j = 0; j < r->Rcur; ++j) {
                 int8_t *s = spin_at(r, r->spin, j);
+                int slot = r->slot ? r->slot[j] : j;
                 for (int v = 0; 32 * v < half; ++v) {
                     uint32_t planes[16];
-                    sweep_planes(r, g, c, j, (uint32_t)v, planes);
+                    sweep_planes(r, g, c, slot, (uint32_t)v, planes);
                     for (int q = 32 * v; q < 32 * v + 32 && q < half; ++q) {
                         int y = q / hw;
                         int x = 2 * (q % hw) + ((y + c) & 1);
@@ -284,7 +287,7 @@ void orc_sweep(orc_run *r, int nsweeps)
                             flip = 1;
                         } else {
                             uint64_t T = (k == 2) ? T2 : T4;
-                            flip = ((uint64_t)site_uniform(r, g, c, j, q, planes) < T);
+                            flip = ((uint64_t)site_uniform(r, g, c, slot, q, planes) < T);
                         }
                         if (flip) {
                             s[y * L + x] = (int8_t)(-si);
@@ -330,8 +333,8 @@ static double weights(const orc_run *r, const int64_t *n, int bmin, int bmax, do
 }
 
 /* Step 2: resample from beta_i-1 to beta_next (Eqs. (Q), (resampling factors)).
- * Returns the new population size, or -1 (state unchanged) if it would exceed
- * the capacity. */
+ * Returns the new population size, or (state unchanged) -1 if it would exceed
+ * the capacity and -2 if no replica would survive. */
 int orc_resample(orc_run *r, double beta_next, double *lnQ_out, int32_t *Emin_out)
 {
     int nb = r->N + 1;
@@ -362,8 +365,11 @@ int orc_resample(orc_run *r, double beta_next, double *lnQ_out, int32_t *Emin_ou
         total += r->counts[j];
     }
     r->counts_n = r->Rcur;
+    free(r->slot);
+    r->slot = NULL;
     free(n); free(w); free(base); free(thr);
     if (total > r->capacity) return -1;
+    if (total == 0) return -2;
     /* compaction: parents in ascending order, copies contiguous */
     int64_t off = 0;
     for (int j = 0; j < r->Rcur; ++j)
@@ -581,6 +587,18 @@ int orc_set_population(orc_run *r, int Rcur, const int8_t *spins, int step, uint
     r->beta = beta;
     r->lnZ = lnZ;
     return 0;
+}
+
+/* Give replica j the random-stream slot slots[j] in later sweeps (NULL
+ * restores slot j); lets a few sampled replicas of a large population be
+ * swept alone.  Resampling clears the table. */
+void orc_set_slots(orc_run *r, const int32_t *slots)
+{
+    free(r->slot);
+    r->slot = NULL;
+    if (!slots) return;
+    r->slot = (int32_t *)malloc(4 * (size_t)r->capacity);
+    memcpy(r->slot, slots, 4 * (size_t)r->Rcur);
 }
 
 /* Full recount of E and M for replica j (invariant check of the incremental

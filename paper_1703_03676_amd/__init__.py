@@ -1,0 +1,233 @@
+"""Population annealing for the 2D Ising model on one MI355X (gfx950).
+
+Thin ctypes binding over ``libpa.so`` (C ABI in ``include/pa.h``).  The
+binding only marshals arguments: every step of the method runs in the
+library's HIP kernels.  PyTorch provides the device workspace and the stream.
+
+Loading requires the HIP extension: if ``libpa.so`` has not been built, or no
+GPU is present when a run is started, an error is raised; there is no CPU
+fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libpa.so")
+
+PA_OK, PA_EINVAL, PA_ENOMEM, PA_ECAPACITY, PA_EHIP, PA_ESTATE, PA_EEXTINCT = 0, -1, -2, -3, -4, -5, -6
+PA_SPIN_INT8, PA_SPIN_BITS = 0, 1
+PA_FLAG_MHR = 1
+LAYOUTS = {"int8": PA_SPIN_INT8, "bits": PA_SPIN_BITS}
+SUPPORTED_L = (16, 32, 64, 128, 256)
+
+
+class PaError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(msg)
+        self.status = status
+
+
+class CapacityError(PaError):
+    pass
+
+
+class ExtinctError(PaError):
+    pass
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("R", ctypes.c_int32), ("capacity", ctypes.c_int32),
+                ("layout", ctypes.c_int32), ("seed", ctypes.c_uint64), ("run_id", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [
+        ("beta", ctypes.c_double), ("e", ctypes.c_double), ("C", ctypes.c_double),
+        ("abs_m", ctypes.c_double), ("m2", ctypes.c_double), ("m4", ctypes.c_double),
+        ("betaF_per_N", ctypes.c_double), ("S_per_N", ctypes.c_double), ("lnQ", ctypes.c_double),
+        ("R", ctypes.c_int64),
+        ("sumE", ctypes.c_int64), ("sumE2", ctypes.c_int64), ("sumAbsM", ctypes.c_int64),
+        ("sumM2", ctypes.c_int64), ("sumM4_lo", ctypes.c_uint64), ("sumM4_hi", ctypes.c_uint64),
+    ]
+
+    def as_dict(self):
+        d = {name: getattr(self, name) for name, _ in self._fields_}
+        d["sumM4"] = (d.pop("sumM4_hi") << 64) | d.pop("sumM4_lo")
+        return d
+
+
+class ResampleInfo(ctypes.Structure):
+    _fields_ = [("lnQ", ctypes.c_double), ("R_new", ctypes.c_int64), ("E_min", ctypes.c_int32)]
+
+
+class StateInfo(ctypes.Structure):
+    _fields_ = [("R", ctypes.c_int64), ("step", ctypes.c_int32), ("sweeps", ctypes.c_uint64),
+                ("beta", ctypes.c_double), ("lnZ", ctypes.c_double)]
+
+
+# Every symbol declared in include/pa.h, with its ctypes signature.
+_P = ctypes.POINTER
+_vp = ctypes.c_void_p
+SIGNATURES = {
+    "pa_workspace_bytes": (ctypes.c_size_t, [_P(Params)]),
+    "pa_init": (ctypes.c_int, [_P(Params), _vp, ctypes.c_size_t, _vp, _P(_vp)]),
+    "pa_sweep": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pa_resample": (ctypes.c_int, [_vp, ctypes.c_double, _P(ResampleInfo)]),
+    "pa_adapt_beta": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, _P(ctypes.c_double), _P(ctypes.c_double)]),
+    "pa_alpha": (ctypes.c_int, [_vp, ctypes.c_double, _P(ctypes.c_double)]),
+    "pa_observables": (ctypes.c_int, [_vp, _P(Obs)]),
+    "pa_reweight": (ctypes.c_int, [_vp, _P(ctypes.c_double), ctypes.c_int32, _P(Obs)]),
+    "pa_state": (ctypes.c_int, [_vp, _P(StateInfo)]),
+    "pa_free": (ctypes.c_int, [_vp]),
+    "pa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "pa_last_error": (ctypes.c_char_p, [_vp]),
+    "pa_download_population": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "pa_upload_population": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, ctypes.c_int32, ctypes.c_uint64,
+                                            ctypes.c_double, ctypes.c_double]),
+    "pa_download_counts": (ctypes.c_int, [_vp, _vp, _P(ctypes.c_int32)]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libpa.so.  torch is imported first so that the library binds to the
+    same HIP runtime instance torch uses."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libpa.so is not built (run __graft_entry__.build() or "
+                               "python paper_1703_03676_amd/build.py)")
+        import torch  # noqa: F401  (binds the HIP runtime before libpa is loaded)
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(status):
+    return lib().pa_strerror(status).decode()
+
+
+def _check(status, handle=None):
+    if status == PA_OK:
+        return
+    msg = strerror(status)
+    if handle:
+        extra = lib().pa_last_error(handle)
+        if extra:
+            msg += ": " + extra.decode()
+    if status == PA_ECAPACITY:
+        raise CapacityError(status, msg)
+    if status == PA_EEXTINCT:
+        raise ExtinctError(status, msg)
+    raise PaError(status, msg)
+
+
+def make_params(L, R, seed, run_id=0, capacity=0, layout="bits", mhr=False):
+    return Params(L=int(L), R=int(R), capacity=int(capacity), layout=LAYOUTS[layout] if isinstance(layout, str) else int(layout),
+                  seed=int(seed), run_id=int(run_id), flags=PA_FLAG_MHR if mhr else 0)
+
+
+def workspace_bytes(params):
+    return lib().pa_workspace_bytes(ctypes.byref(params))
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Run:
+    """One PA run on the current GPU (C-ABI handle + torch-owned workspace)."""
+
+    def __init__(self, L, R, seed, run_id=0, capacity=0, layout="bits", mhr=False, stream=None, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU available: libpa runs on the GPU only")
+        self.params = make_params(L, R, seed, run_id, capacity, layout, mhr)
+        nbytes = workspace_bytes(self.params)
+        if nbytes == 0:
+            raise PaError(PA_EINVAL, "invalid parameters")
+        self.L, self.N, self.R = L, L * L, R
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        h = ctypes.c_void_p()
+        _check(lib().pa_init(ctypes.byref(self.params), ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self.capacity = self.params.capacity or default_capacity(R)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pa_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    # --- the method -------------------------------------------------------
+    def sweep(self, nsweeps):
+        _check(lib().pa_sweep(self.h, int(nsweeps)), self.h)
+
+    def resample(self, beta_next):
+        info = ResampleInfo()
+        _check(lib().pa_resample(self.h, float(beta_next), ctypes.byref(info)), self.h)
+        return {"R_new": info.R_new, "lnQ": info.lnQ, "E_min": info.E_min}
+
+    def adapt_beta(self, alpha_star, beta_f):
+        b, a = ctypes.c_double(), ctypes.c_double()
+        _check(lib().pa_adapt_beta(self.h, float(alpha_star), float(beta_f), ctypes.byref(b), ctypes.byref(a)), self.h)
+        return b.value
+
+    def alpha(self, beta_prime):
+        a = ctypes.c_double()
+        _check(lib().pa_alpha(self.h, float(beta_prime), ctypes.byref(a)), self.h)
+        return a.value
+
+    def observables(self):
+        o = Obs()
+        _check(lib().pa_observables(self.h, ctypes.byref(o)), self.h)
+        return o.as_dict()
+
+    def reweight(self, betas):
+        betas = np.ascontiguousarray(betas, dtype=np.float64)
+        out = (Obs * max(len(betas), 1))()
+        _check(lib().pa_reweight(self.h, betas.ctypes.data_as(_P(ctypes.c_double)), len(betas), out), self.h)
+        return [out[k].as_dict() for k in range(len(betas))]
+
+    def state(self):
+        s = StateInfo()
+        _check(lib().pa_state(self.h, ctypes.byref(s)), self.h)
+        return {"R": s.R, "step": s.step, "sweeps": s.sweeps, "beta": s.beta, "lnZ": s.lnZ}
+
+    # --- test hooks ---------------------------------------------------------
+    def download_population(self):
+        n = self.state()["R"]
+        s = np.empty((n, self.L, self.L), np.int8)
+        E = np.empty(n, np.int32)
+        M = np.empty(n, np.int32)
+        _check(lib().pa_download_population(self.h, _ptr(s), _ptr(E), _ptr(M)), self.h)
+        return s, E, M
+
+    def upload_population(self, spins, step=0, sweeps=0, beta=0.0, lnZ=0.0):
+        spins = np.ascontiguousarray(spins, dtype=np.int8)
+        assert spins.ndim == 3 and spins.shape[1:] == (self.L, self.L)
+        _check(lib().pa_upload_population(self.h, spins.shape[0], _ptr(spins), int(step), int(sweeps),
+                                          float(beta), float(lnZ)), self.h)
+
+    def download_counts(self, capacity):
+        buf = np.empty(capacity, np.uint32)
+        n = ctypes.c_int32()
+        _check(lib().pa_download_counts(self.h, _ptr(buf), ctypes.byref(n)), self.h)
+        return buf[: n.value].copy()
+
+
+def default_capacity(R):
+    return R + int(np.ceil(10.0 * np.sqrt(R))) + 64

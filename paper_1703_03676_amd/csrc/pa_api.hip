@@ -1,0 +1,651 @@
+// C ABI of libpa (declared in include/pa.h): run state, validation, workspace
+// layout, and the FP64 host arithmetic of the method (Metropolis thresholds,
+// Eq. (Q) weights and resampling tables, observables, adaptive step,
+// multi-histogram reweighting).  Everything per replica runs in the kernels of
+// pa_kernels.hip; the host works only on energy bins and a few scalars.
+//
+// FP64 results that decide integers (thresholds, copy-count tables, the
+// bisection) are computed with a fixed operation order, ascending energy bins,
+// and without contraction (-ffp-contract=off), so a run is reproducible bit for
+// bit from its seed and schedule.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pa.h"
+#include "pa_internal.h"
+
+using pa::DevMhr;
+using pa::DevStats;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool lattice_supported(int L) { return L == 16 || L == 32 || L == 64 || L == 128 || L == 256; }
+
+int32_t default_capacity(int32_t R)
+{
+    return R + (int32_t)std::ceil(10.0 * std::sqrt((double)R)) + 64;
+}
+
+struct Layout {
+    size_t spin[2], E[2], M[2], counts, parent, bsum, tbl, stats, mhr, total;
+    size_t rep_bytes;
+    int32_t capacity, nbins, nblk;
+};
+
+// Validates the parameters and places every device array in the workspace.
+bool make_layout(const pa_params* p, Layout* lo)
+{
+    if (!p || !lattice_supported(p->L) || p->R < 1) return false;
+    if (p->layout != PA_SPIN_INT8 && p->layout != PA_SPIN_BITS) return false;
+    if (p->flags & ~(uint32_t)PA_FLAG_MHR) return false;
+    const int64_t cap = p->capacity ? p->capacity : default_capacity(p->R);
+    if (cap < p->R || cap > (int64_t)1 << 30) return false;
+    const int64_t N = (int64_t)p->L * p->L;
+    lo->capacity = (int32_t)cap;
+    lo->nbins = (int32_t)N + 1;
+    lo->rep_bytes = (p->layout == PA_SPIN_INT8) ? (size_t)N : (size_t)N / 8;
+    lo->nblk = (int32_t)((cap + pa::kBlock - 1) / pa::kBlock);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    for (int b = 0; b < 2; ++b) {
+        lo->spin[b] = take((size_t)cap * lo->rep_bytes);
+        lo->E[b] = take((size_t)cap * 4);
+        lo->M[b] = take((size_t)cap * 4);
+    }
+    lo->counts = take((size_t)cap * 4);
+    lo->parent = take((size_t)cap * 4);
+    lo->bsum = take((size_t)lo->nblk * 4 + 4);
+    lo->tbl = take((size_t)lo->nbins * 8);
+    lo->stats = take(sizeof(DevStats) + (size_t)lo->nbins * 4);
+    lo->mhr = (p->flags & PA_FLAG_MHR) ? take((size_t)lo->nbins * 40) : o;
+    lo->total = o;
+    return true;
+}
+
+}  // namespace
+
+struct pa_run {
+    pa_params p;
+    Layout lo;
+    int L, N, nbins;
+    hipStream_t stream;
+    uint8_t* ws;
+    uint8_t* spin[2];
+    int32_t* E[2];
+    int32_t* M[2];
+    int cur;
+    uint32_t *counts, *parent, *bsum, *tbl, *hist;
+    DevStats* stats;
+    DevMhr mhr;
+    // host-side run state
+    int64_t R_cur;
+    int32_t step;
+    uint64_t sweeps;
+    double beta, lnZ, lnQ_last;
+    int32_t counts_n;
+    bool broken;
+    std::string last_error;
+    uint64_t version, stats_version;
+    DevStats h_stats;
+    std::vector<uint32_t> h_hist;
+    uint8_t* pinned;
+    size_t pinned_bytes;
+    std::vector<double> m_beta, m_lnZ;
+    std::vector<int64_t> m_R;
+};
+
+namespace {
+
+pa_status fail_hip(pa_run* r, hipError_t e, const char* what)
+{
+    r->broken = true;
+    r->last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return PA_EHIP;
+}
+
+#define HIPCHK(expr)                                        \
+    do {                                                    \
+        const hipError_t e_ = (expr);                       \
+        if (e_ != hipSuccess) return fail_hip(r, e_, #expr); \
+    } while (0)
+
+pa_status usable(const pa_run* r)
+{
+    if (!r) return PA_EINVAL;
+    return r->broken ? PA_ESTATE : PA_OK;
+}
+
+int32_t energy_of_bin(const pa_run* r, int b) { return 4 * b - 2 * r->N; }
+
+// Metropolis thresholds ceil(2^32 exp(-2 beta k)) for k = 2 and k = 4, split
+// into the high part (compared bit-plane by bit-plane) and the low 16 bits.
+void thresholds(double beta, pa::SweepArgs* a)
+{
+    const uint64_t t2 = (uint64_t)std::ceil(std::ldexp(std::exp(-4.0 * beta), 32));
+    const uint64_t t4 = (uint64_t)std::ceil(std::ldexp(std::exp(-8.0 * beta), 32));
+    a->t2h = (uint32_t)(t2 >> 16);
+    a->t2l = (uint32_t)(t2 & 0xFFFFu);
+    a->t4h = (uint32_t)(t4 >> 16);
+    a->t4l = (uint32_t)(t4 & 0xFFFFu);
+}
+
+void key_of(const pa_run* r, uint32_t* k0, uint32_t* k1)
+{
+    *k0 = (uint32_t)r->p.seed;
+    *k1 = (uint32_t)(r->p.seed >> 32) ^ r->p.run_id;
+}
+
+pa_status launch_sweeps(pa_run* r, int32_t nsweeps, bool init)
+{
+    pa::SweepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.spin = r->spin[r->cur];
+    a.E = r->E[r->cur];
+    a.M = r->M[r->cur];
+    a.n_rep = (int32_t)r->R_cur;
+    a.nsweeps = nsweeps;
+    a.g0 = (uint32_t)r->sweeps;
+    key_of(r, &a.key0, &a.key1);
+    thresholds(r->beta, &a);
+    a.init = init ? 1 : 0;
+    HIPCHK(pa::launch_sweep(r->L, r->p.layout, a, r->stream));
+    return PA_OK;
+}
+
+// Brings the histogram and the integer sums of the current population to the
+// host.  With `record` the measurement is also added to the multi-histogram
+// accumulators (only then is a cached result not reused).
+pa_status refresh_stats(pa_run* r, bool record)
+{
+    if (!record && r->stats_version == r->version) return PA_OK;
+    HIPCHK(pa::launch_stats_reset(r->stats, r->hist, r->nbins, r->stream));
+    HIPCHK(pa::launch_stats(r->E[r->cur], r->M[r->cur], (int32_t)r->R_cur, r->N, r->stats, r->hist, r->nbins,
+                            record ? 1 : 0, r->mhr, r->stream));
+    const size_t bytes = sizeof(DevStats) + (size_t)r->nbins * 4;
+    HIPCHK(hipMemcpyAsync(r->pinned, r->stats, bytes, hipMemcpyDeviceToHost, r->stream));
+    HIPCHK(hipStreamSynchronize(r->stream));
+    std::memcpy(&r->h_stats, r->pinned, sizeof(DevStats));
+    std::memcpy(r->h_hist.data(), r->pinned + sizeof(DevStats), (size_t)r->nbins * 4);
+    if (r->h_stats.emin < -2 * r->N || r->h_stats.emax > 2 * r->N || r->h_stats.emin > r->h_stats.emax) {
+        r->broken = true;
+        r->last_error = "population energies out of range";
+        return PA_ESTATE;
+    }
+    r->stats_version = r->version;
+    return PA_OK;
+}
+
+// W = sum over occupied bins (ascending) of n(b) w(b), w(b) = exp(-dbeta (E_b - E_min)).
+double weight_sum(const pa_run* r, int bmin, int bmax, double dbeta, std::vector<double>* w)
+{
+    const int32_t Emin = energy_of_bin(r, bmin);
+    double W = 0.0;
+    for (int b = bmin; b <= bmax; ++b) {
+        const uint32_t n = r->h_hist[b];
+        if (n == 0) continue;
+        const double d = (double)(energy_of_bin(r, b) - Emin);
+        const double wb = std::exp(-(dbeta * d));
+        if (w) (*w)[b - bmin] = wb;
+        W += (double)n * wb;
+    }
+    return W;
+}
+
+int bin_lo(const pa_run* r) { return (r->h_stats.emin + 2 * r->N) / 4; }
+int bin_hi(const pa_run* r) { return (r->h_stats.emax + 2 * r->N) / 4; }
+
+// Histogram overlap alpha(beta_i, beta') (Sec. 2.3) over energy bins.
+double overlap(const pa_run* r, double beta_prime)
+{
+    const int bmin = bin_lo(r), bmax = bin_hi(r);
+    std::vector<double> w((size_t)(bmax - bmin + 1));
+    const double W = weight_sum(r, bmin, bmax, beta_prime - r->beta, &w);
+    double acc = 0.0;
+    for (int b = bmin; b <= bmax; ++b) {
+        const uint32_t n = r->h_hist[b];
+        if (n == 0) continue;
+        const double tau = ((double)r->p.R * w[b - bmin]) / W;
+        acc += (double)n * (tau < 1.0 ? tau : 1.0);
+    }
+    return acc / (double)r->R_cur;
+}
+
+double u128_to_double(uint64_t lo, uint64_t hi)
+{
+    const unsigned __int128 v = ((unsigned __int128)hi << 64) | lo;
+    return (double)v;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pa_workspace_bytes(const pa_params* p)
+{
+    Layout lo;
+    return make_layout(p, &lo) ? lo.total : 0;
+}
+
+const char* pa_strerror(pa_status s)
+{
+    switch (s) {
+    case PA_OK: return "success";
+    case PA_EINVAL: return "invalid argument";
+    case PA_ENOMEM: return "workspace too small or host allocation failed";
+    case PA_ECAPACITY: return "population exceeds capacity";
+    case PA_EHIP: return "HIP runtime error";
+    case PA_ESTATE: return "run unusable or call out of order";
+    case PA_EEXTINCT: return "resampling would leave no replica";
+    }
+    return "unknown status";
+}
+
+const char* pa_last_error(const pa_run* r) { return r ? r->last_error.c_str() : ""; }
+
+pa_status pa_init(const pa_params* p, void* d_workspace, size_t bytes, void* hip_stream, pa_run** out)
+{
+    if (!out) return PA_EINVAL;
+    *out = nullptr;
+    Layout lo;
+    if (!make_layout(p, &lo) || !d_workspace) return PA_EINVAL;
+    if (((uintptr_t)d_workspace) % kAlign != 0) return PA_EINVAL;
+    if (bytes < lo.total) return PA_ENOMEM;
+    pa_run* r = new (std::nothrow) pa_run();
+    if (!r) return PA_ENOMEM;
+    r->p = *p;
+    r->p.capacity = lo.capacity;
+    r->lo = lo;
+    r->L = p->L;
+    r->N = p->L * p->L;
+    r->nbins = lo.nbins;
+    r->stream = (hipStream_t)hip_stream;
+    uint8_t* ws = (uint8_t*)d_workspace;
+    r->ws = ws;
+    for (int b = 0; b < 2; ++b) {
+        r->spin[b] = ws + lo.spin[b];
+        r->E[b] = (int32_t*)(ws + lo.E[b]);
+        r->M[b] = (int32_t*)(ws + lo.M[b]);
+    }
+    r->counts = (uint32_t*)(ws + lo.counts);
+    r->parent = (uint32_t*)(ws + lo.parent);
+    r->bsum = (uint32_t*)(ws + lo.bsum);
+    r->tbl = (uint32_t*)(ws + lo.tbl);
+    r->stats = (DevStats*)(ws + lo.stats);
+    r->hist = (uint32_t*)(ws + lo.stats + sizeof(DevStats));
+    if (p->flags & PA_FLAG_MHR) {
+        uint64_t* m = (uint64_t*)(ws + lo.mhr);
+        r->mhr.H = m;
+        r->mhr.SA = m + r->nbins;
+        r->mhr.SM2 = m + 2 * (size_t)r->nbins;
+        r->mhr.SM4 = m + 3 * (size_t)r->nbins;
+    } else {
+        r->mhr = DevMhr{nullptr, nullptr, nullptr, nullptr};
+    }
+    r->h_hist.assign((size_t)r->nbins, 0u);
+    r->pinned_bytes = sizeof(DevStats) + (size_t)r->nbins * 8;
+    if (hipHostMalloc((void**)&r->pinned, r->pinned_bytes, hipHostMallocDefault) != hipSuccess) {
+        delete r;
+        return PA_ENOMEM;
+    }
+    r->cur = 0;
+    r->R_cur = p->R;
+    r->step = 0;
+    r->sweeps = 0;
+    r->beta = 0.0;
+    r->lnZ = (double)r->N * std::log(2.0);
+    r->lnQ_last = 0.0;
+    r->counts_n = 0;
+    r->version = 1;
+    r->stats_version = 0;
+    *out = r;
+    if (p->flags & PA_FLAG_MHR) {
+        pa_status st = PA_OK;
+        const hipError_t e = pa::launch_fill_u32((uint32_t*)r->mhr.H, 0u, (size_t)r->nbins * 10, r->stream);
+        if (e != hipSuccess) st = fail_hip(r, e, "zero multi-histogram accumulators");
+        if (st != PA_OK) return st;
+    }
+    return launch_sweeps(r, 0, true);
+}
+
+pa_status pa_sweep(pa_run* r, int32_t nsweeps)
+{
+    pa_status st = usable(r);
+    if (st != PA_OK) return st;
+    if (nsweeps < 0 || r->sweeps + (uint64_t)nsweeps >= ((uint64_t)1 << 31)) return PA_EINVAL;
+    if (nsweeps == 0) return PA_OK;
+    st = launch_sweeps(r, nsweeps, false);
+    if (st != PA_OK) return st;
+    r->sweeps += (uint64_t)nsweeps;
+    r->version += 1;
+    return PA_OK;
+}
+
+pa_status pa_resample(pa_run* r, double beta_next, pa_resample_info* out)
+{
+    pa_status st = usable(r);
+    if (st != PA_OK) return st;
+    if (!std::isfinite(beta_next) || beta_next < r->beta) return PA_EINVAL;
+    st = refresh_stats(r, false);
+    if (st != PA_OK) return st;
+
+    // Eq. (Q) with the E_min shift, and the tables of Eq. (resampling factors).
+    const int bmin = bin_lo(r), bmax = bin_hi(r), nwin = bmax - bmin + 1;
+    const double dbeta = beta_next - r->beta;
+    std::vector<double> w((size_t)nwin);
+    const double W = weight_sum(r, bmin, bmax, dbeta, &w);
+    const int32_t Emin = energy_of_bin(r, bmin);
+    const double lnQ = std::log(W) - std::log((double)r->R_cur) - dbeta * (double)Emin;
+    uint32_t* tab = (uint32_t*)r->pinned;
+    for (int b = bmin; b <= bmax; ++b) {
+        uint32_t base = 0, thr = 0;
+        if (r->h_hist[b] != 0) {
+            const double tau = ((double)r->p.R * w[b - bmin]) / W;
+            const double fl = std::floor(tau);
+            base = (uint32_t)fl;
+            thr = (uint32_t)std::floor(std::ldexp(tau - fl, 32));
+        }
+        tab[2 * (b - bmin)] = base;
+        tab[2 * (b - bmin) + 1] = thr;
+    }
+    HIPCHK(hipMemcpyAsync(r->tbl, tab, (size_t)nwin * 8, hipMemcpyHostToDevice, r->stream));
+
+    uint32_t k0, k1;
+    key_of(r, &k0, &k1);
+    const int32_t n = (int32_t)r->R_cur;
+    const int32_t nblk = (n + pa::kBlock - 1) / pa::kBlock;
+    const uint32_t step = (uint32_t)(r->step + 1);
+    HIPCHK(pa::launch_counts(r->E[r->cur], n, r->N, bmin, nwin, r->tbl, step, k0, k1, r->counts, r->bsum,
+                             r->stream));
+    HIPCHK(pa::launch_scan_blocks(r->bsum, nblk, r->stats, r->stream));
+    uint32_t* rn = (uint32_t*)(r->pinned + r->pinned_bytes - 8);
+    HIPCHK(hipMemcpyAsync(rn, &r->stats->r_new, 4, hipMemcpyDeviceToHost, r->stream));
+    HIPCHK(hipStreamSynchronize(r->stream));
+    const int64_t R_new = *rn;
+    r->counts_n = n;
+    r->stats_version = 0;  // the stats block now holds the resampling total
+    if (R_new > r->lo.capacity) return PA_ECAPACITY;
+    if (R_new == 0) return PA_EEXTINCT;
+
+    const int nxt = r->cur ^ 1;
+    HIPCHK(pa::launch_scatter(r->counts, r->bsum, n, r->parent, r->stream));
+    HIPCHK(pa::launch_copy(r->spin[r->cur], r->E[r->cur], r->M[r->cur], r->parent, (int32_t)R_new, r->lo.rep_bytes,
+                           r->spin[nxt], r->E[nxt], r->M[nxt], r->stream));
+    r->cur = nxt;
+    r->R_cur = R_new;
+    r->step += 1;
+    r->beta = beta_next;
+    r->lnZ += lnQ;
+    r->lnQ_last = lnQ;
+    r->version += 1;
+    if (out) {
+        out->lnQ = lnQ;
+        out->R_new = R_new;
+        out->E_min = Emin;
+    }
+    return PA_OK;
+}
+
+pa_status pa_alpha(pa_run* r, double beta_prime, double* alpha)
+{
+    pa_status st = usable(r);
+    if (st != PA_OK) return st;
+    if (!alpha || !std::isfinite(beta_prime)) return PA_EINVAL;
+    st = refresh_stats(r, false);
+    if (st != PA_OK) return st;
+    *alpha = overlap(r, beta_prime);
+    return PA_OK;
+}
+
+pa_status pa_adapt_beta(pa_run* r, double alpha_star, double beta_f, double* beta_next, double* alpha_at_next)
+{
+    pa_status st = usable(r);
+    if (st != PA_OK) return st;
+    if (!beta_next || !(alpha_star > 0.0 && alpha_star < 1.0) || !std::isfinite(beta_f) || beta_f < r->beta)
+        return PA_EINVAL;
+    st = refresh_stats(r, false);
+    if (st != PA_OK) return st;
+    const double a_f = overlap(r, beta_f);
+    if (a_f >= alpha_star) {
+        *beta_next = beta_f;
+        if (alpha_at_next) *alpha_at_next = a_f;
+        return PA_OK;
+    }
+    double lo = r->beta, hi = beta_f;
+    for (int it = 0; it < 50; ++it) {
+        const double mid = lo + 0.5 * (hi - lo);
+        if (overlap(r, mid) >= alpha_star)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    if (lo == r->beta) return PA_EINVAL;
+    *beta_next = lo;
+    if (alpha_at_next) *alpha_at_next = overlap(r, lo);
+    return PA_OK;
+}
+
+pa_status pa_observables(pa_run* r, pa_obs* o)
+{
+    pa_status st = usable(r);
+    if (st != PA_OK) return st;
+    if (!o) return PA_EINVAL;
+    const bool record = (r->p.flags & PA_FLAG_MHR) != 0;
+    st = refresh_stats(r, record);
+    if (st != PA_OK) return st;
+    const DevStats& s = r->h_stats;
+    const int64_t sE = (int64_t)s.sumE, sE2 = (int64_t)s.sumE2;
+    const double N = (double)r->N, R = (double)r->R_cur, beta = r->beta;
+    const __int128 D = (__int128)r->R_cur * (__int128)sE2 - (__int128)sE * (__int128)sE;
+    o->beta = beta;
+    o->e = (double)sE / (R * N);
+    o->C = (beta * beta * (double)D) / (N * R * R);
+    o->abs_m = (double)(int64_t)s.sumAbsM / (R * N);
+    o->m2 = (double)(int64_t)s.sumM2 / (R * N * N);
+    o->m4 = u128_to_double(s.sumM4_lo, s.sumM4_hi) / (R * N * N * N * N);
+    o->betaF_per_N = -r->lnZ / N;
+    o->S_per_N = beta * o->e + r->lnZ / N;
+    o->lnQ = r->lnQ_last;
+    o->R = r->R_cur;
+    o->sumE = sE;
+    o->sumE2 = sE2;
+    o->sumAbsM = (int64_t)s.sumAbsM;
+    o->sumM2 = (int64_t)s.sumM2;
+    o->sumM4_lo = s.sumM4_lo;
+    o->sumM4_hi = s.sumM4_hi;
+    if (record) {
+        r->m_beta.push_back(beta);
+        r->m_lnZ.push_back(r->lnZ);
+        r->m_R.push_back(r->R_cur);
+    }
+    return PA_OK;
+}
+
+pa_status pa_reweight(pa_run* r, const double* betas, int32_t nb, pa_obs* out)
+{
+    pa_status st = usable(r);
+    if (st != PA_OK) return st;
+    if (!(r->p.flags & PA_FLAG_MHR) || nb < 0 || (nb > 0 && (!betas || !out)) || r->m_beta.empty())
+        return PA_EINVAL;
+    const size_t nbins = (size_t)r->nbins;
+    std::vector<uint64_t> acc(5 * nbins);
+    HIPCHK(hipMemcpyAsync(acc.data(), r->mhr.H, acc.size() * 8, hipMemcpyDeviceToHost, r->stream));
+    HIPCHK(hipStreamSynchronize(r->stream));
+    const uint64_t* H = acc.data();
+    const uint64_t* SA = H + nbins;
+    const uint64_t* SM2 = H + 2 * nbins;
+    const uint64_t* SM4 = H + 3 * nbins;
+    const double N = (double)r->N;
+    const size_t nm = r->m_beta.size();
+
+    // ln Omega(E) = ln H(E) - ln sum_i R_i exp(-ln Z_i - beta_i E)   (Sec. 2.4)
+    std::vector<double> lnOmega(nbins, 0.0), lw(nbins, 0.0), terms(nm);
+    for (size_t b = 0; b < nbins; ++b) {
+        if (H[b] == 0) continue;
+        const double E = (double)energy_of_bin(r, (int)b);
+        double mx = -INFINITY;
+        for (size_t i = 0; i < nm; ++i) {
+            terms[i] = std::log((double)r->m_R[i]) - r->m_lnZ[i] - r->m_beta[i] * E;
+            if (terms[i] > mx) mx = terms[i];
+        }
+        double s = 0.0;
+        for (size_t i = 0; i < nm; ++i) s += std::exp(terms[i] - mx);
+        lnOmega[b] = std::log((double)H[b]) - (mx + std::log(s));
+    }
+    for (int32_t k = 0; k < nb; ++k) {
+        const double beta = betas[k];
+        double mx = -INFINITY;
+        for (size_t b = 0; b < nbins; ++b) {
+            if (H[b] == 0) continue;
+            lw[b] = lnOmega[b] - beta * (double)energy_of_bin(r, (int)b);
+            if (lw[b] > mx) mx = lw[b];
+        }
+        double s = 0.0;
+        for (size_t b = 0; b < nbins; ++b)
+            if (H[b] != 0) s += std::exp(lw[b] - mx);
+        const double lnZ = mx + std::log(s);
+        double mE = 0.0, mA = 0.0, mM2 = 0.0, mM4 = 0.0;
+        for (size_t b = 0; b < nbins; ++b) {
+            if (H[b] == 0) continue;
+            const double p = std::exp(lw[b] - lnZ);
+            const double h = (double)H[b];
+            mE += p * (double)energy_of_bin(r, (int)b);
+            mA += p * ((double)SA[b] / h);
+            mM2 += p * ((double)SM2[b] / h);
+            mM4 += p * (u128_to_double(SM4[2 * b], SM4[2 * b + 1]) / h);
+        }
+        double var = 0.0;
+        for (size_t b = 0; b < nbins; ++b) {
+            if (H[b] == 0) continue;
+            const double p = std::exp(lw[b] - lnZ);
+            const double d = (double)energy_of_bin(r, (int)b) - mE;
+            var += p * d * d;
+        }
+        pa_obs* o = &out[k];
+        std::memset(o, 0, sizeof(*o));
+        o->beta = beta;
+        o->e = mE / N;
+        o->C = beta * beta * var / N;
+        o->abs_m = mA / N;
+        o->m2 = mM2 / (N * N);
+        o->m4 = mM4 / (N * N * N * N);
+        o->betaF_per_N = -lnZ / N;
+        o->S_per_N = beta * o->e + lnZ / N;
+    }
+    return PA_OK;
+}
+
+pa_status pa_state(const pa_run* r, pa_state_info* out)
+{
+    if (!r || !out) return PA_EINVAL;
+    out->R = r->R_cur;
+    out->step = r->step;
+    out->sweeps = r->sweeps;
+    out->beta = r->beta;
+    out->lnZ = r->lnZ;
+    return PA_OK;
+}
+
+pa_status pa_free(pa_run* r)
+{
+    if (!r) return PA_OK;
+    if (r->pinned) (void)hipHostFree(r->pinned);
+    delete r;
+    return PA_OK;
+}
+
+pa_status pa_download_population(pa_run* r, int8_t* spins, int32_t* E, int32_t* M)
+{
+    pa_status st = usable(r);
+    if (st != PA_OK) return st;
+    const size_t n = (size_t)r->R_cur;
+    if (E) HIPCHK(hipMemcpyAsync(E, r->E[r->cur], n * 4, hipMemcpyDeviceToHost, r->stream));
+    if (M) HIPCHK(hipMemcpyAsync(M, r->M[r->cur], n * 4, hipMemcpyDeviceToHost, r->stream));
+    if (spins) {
+        if (r->p.layout == PA_SPIN_INT8) {
+            HIPCHK(hipMemcpyAsync(spins, r->spin[r->cur], n * (size_t)r->N, hipMemcpyDeviceToHost, r->stream));
+        } else {
+            std::vector<uint32_t> words(n * (size_t)r->N / 32);
+            HIPCHK(hipMemcpyAsync(words.data(), r->spin[r->cur], words.size() * 4, hipMemcpyDeviceToHost, r->stream));
+            HIPCHK(hipStreamSynchronize(r->stream));
+            const int L = r->L, half = r->N / 2, hw = L / 2;
+            for (size_t j = 0; j < n; ++j) {
+                const uint32_t* wj = words.data() + j * (size_t)(r->N / 32);
+                int8_t* sj = spins + j * (size_t)r->N;
+                for (int c = 0; c < 2; ++c)
+                    for (int q = 0; q < half; ++q) {
+                        const int y = q / hw, x = 2 * (q % hw) + ((y + c) & 1);
+                        const uint32_t bit = (wj[c * (half / 32) + (q >> 5)] >> (q & 31)) & 1u;
+                        sj[y * L + x] = bit ? -1 : 1;
+                    }
+            }
+        }
+    }
+    HIPCHK(hipStreamSynchronize(r->stream));
+    return PA_OK;
+}
+
+pa_status pa_upload_population(pa_run* r, int32_t R_cur, const int8_t* spins, int32_t step, uint64_t sweeps,
+                               double beta, double lnZ)
+{
+    pa_status st = usable(r);
+    if (st != PA_OK) return st;
+    if (!spins || R_cur < 1 || R_cur > r->lo.capacity || step < 0 || !std::isfinite(beta) || beta < 0.0 ||
+        sweeps >= ((uint64_t)1 << 31))
+        return PA_EINVAL;
+    const size_t n = (size_t)R_cur, N = (size_t)r->N;
+    for (size_t i = 0; i < n * N; ++i)
+        if (spins[i] != 1 && spins[i] != -1) return PA_EINVAL;
+    if (r->p.layout == PA_SPIN_INT8) {
+        HIPCHK(hipMemcpyAsync(r->spin[r->cur], spins, n * N, hipMemcpyHostToDevice, r->stream));
+        HIPCHK(hipStreamSynchronize(r->stream));
+    } else {
+        std::vector<uint32_t> words(n * N / 32, 0u);
+        const int L = r->L, half = r->N / 2, hw = L / 2;
+        for (size_t j = 0; j < n; ++j) {
+            uint32_t* wj = words.data() + j * (N / 32);
+            const int8_t* sj = spins + j * N;
+            for (int c = 0; c < 2; ++c)
+                for (int q = 0; q < half; ++q) {
+                    const int y = q / hw, x = 2 * (q % hw) + ((y + c) & 1);
+                    if (sj[y * L + x] < 0) wj[c * (half / 32) + (q >> 5)] |= 1u << (q & 31);
+                }
+        }
+        HIPCHK(hipMemcpyAsync(r->spin[r->cur], words.data(), words.size() * 4, hipMemcpyHostToDevice, r->stream));
+        HIPCHK(hipStreamSynchronize(r->stream));
+    }
+    r->R_cur = R_cur;
+    r->step = step;
+    r->sweeps = sweeps;
+    r->beta = beta;
+    r->lnZ = lnZ;
+    r->lnQ_last = 0.0;
+    r->version += 1;
+    return launch_sweeps(r, 0, false);  // recount E and M on the device
+}
+
+pa_status pa_download_counts(pa_run* r, uint32_t* counts, int32_t* n)
+{
+    pa_status st = usable(r);
+    if (st != PA_OK) return st;
+    if (!counts || !n) return PA_EINVAL;
+    *n = r->counts_n;
+    if (r->counts_n > 0) {
+        HIPCHK(hipMemcpyAsync(counts, r->counts, (size_t)r->counts_n * 4, hipMemcpyDeviceToHost, r->stream));
+        HIPCHK(hipStreamSynchronize(r->stream));
+    }
+    return PA_OK;
+}
+
+}  // extern "C"

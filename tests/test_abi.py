@@ -1,0 +1,85 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+include/pa.h declares, and validates arguments before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1703_03676_amd as pa
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pa.h")
+
+
+def declared_functions():
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    return sorted(set(re.findall(r"\b(pa_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 15
+    raw = ctypes.CDLL(pa.LIB_PATH)
+    for n in names:
+        assert hasattr(raw, n), n
+    assert set(names) == set(pa.SIGNATURES)
+
+
+def test_status_codes_match_header():
+    txt = open(HEADER).read()
+    for name, val in re.findall(r"(PA_E[A-Z]+|PA_OK)\s*=\s*(-?\d+)", txt):
+        assert getattr(pa, name) == int(val)
+        assert pa.strerror(int(val)) != "unknown status"
+
+
+def test_workspace_bytes_validation():
+    ok = pa.make_params(64, 20000, 1)
+    n_bits = pa.workspace_bytes(ok)
+    n_int8 = pa.workspace_bytes(pa.make_params(64, 20000, 1, layout="int8"))
+    assert 2 * 20000 * 512 < n_bits < n_int8
+    assert n_int8 > 2 * 20000 * 4096
+    assert pa.workspace_bytes(pa.make_params(64, 20000, 1, mhr=True)) > n_bits
+    for bad in (pa.make_params(63, 10, 1), pa.make_params(48, 10, 1), pa.make_params(8, 10, 1),
+                pa.make_params(512, 10, 1), pa.make_params(16, 0, 1), pa.make_params(16, 10, 1, capacity=5),
+                pa.make_params(16, 10, 1, layout=7)):
+        assert pa.workspace_bytes(bad) == 0
+    bad_flags = pa.make_params(16, 10, 1)
+    bad_flags.flags = 2
+    assert pa.workspace_bytes(bad_flags) == 0
+    for L in pa.SUPPORTED_L:
+        assert pa.workspace_bytes(pa.make_params(L, 3, 1)) > 0
+
+
+def test_init_validates_before_device_work():
+    lib = pa.lib()
+    h = ctypes.c_void_p()
+    p = pa.make_params(16, 10, 1)
+    need = pa.workspace_bytes(p)
+    # NULL workspace, misaligned workspace, too small workspace, invalid params:
+    # all rejected on the host before any HIP call.
+    assert lib.pa_init(ctypes.byref(p), None, need, None, ctypes.byref(h)) == pa.PA_EINVAL
+    assert lib.pa_init(ctypes.byref(p), ctypes.c_void_p(4096 + 8), need, None, ctypes.byref(h)) == pa.PA_EINVAL
+    assert lib.pa_init(ctypes.byref(p), ctypes.c_void_p(4096), need - 1, None, ctypes.byref(h)) == pa.PA_ENOMEM
+    bad = pa.make_params(17, 10, 1)
+    assert lib.pa_init(ctypes.byref(bad), ctypes.c_void_p(4096), 1 << 30, None, ctypes.byref(h)) == pa.PA_EINVAL
+    assert lib.pa_init(ctypes.byref(p), ctypes.c_void_p(4096), need, None, None) == pa.PA_EINVAL
+    assert not h.value
+
+
+def test_null_handle():
+    lib = pa.lib()
+    assert lib.pa_sweep(None, 1) == pa.PA_EINVAL
+    assert lib.pa_resample(None, 0.1, None) == pa.PA_EINVAL
+    assert lib.pa_observables(None, None) == pa.PA_EINVAL
+    assert lib.pa_state(None, None) == pa.PA_EINVAL
+    assert lib.pa_free(None) == pa.PA_OK
+    assert lib.pa_last_error(None) == b""
+
+
+def test_binding_refuses_to_run_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(RuntimeError):
+        pa.Run(16, 10, seed=1)

@@ -1,0 +1,292 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Spins, energies, magnetisations, copy counts, population sizes and the
+adaptive inverse temperatures must be bit-identical; FP64 quantities derived
+from them (free energy, entropy, observables, reweighting) agree to 1e-12
+relative.  Inputs are seeded: the method's own initial state, or synthetic
+populations from tests/inputs.py.
+"""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+
+pa = pytest.importorskip("paper_1703_03676_amd")
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+LAYOUTS = ["int8", "bits"]
+# population sizes spanning several blocks with a ragged last one
+R_OF_L = {16: 300, 32: 70, 64: 9, 128: 5, 256: 3}
+FP_REL = 1e-12
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _same_population(g, o):
+    gs, gE, gM = g.download_population()
+    os_, oE, oM = o.get_population()
+    assert gs.shape == os_.shape
+    assert np.array_equal(gE, oE)
+    assert np.array_equal(gM, oM)
+    assert np.array_equal(gs, os_)
+
+
+def _close(a, b, rel=FP_REL):
+    return a == b or abs(a - b) <= rel * max(abs(a), abs(b))
+
+
+def _same_obs(go, oo):
+    for k in ("sumE", "sumE2", "sumAbsM", "sumM2", "sumM4", "R"):
+        assert go[k] == oo[k], k
+    for k in ("beta", "e", "C", "abs_m", "m2", "m4", "betaF_per_N", "S_per_N", "lnQ"):
+        assert _close(go[k], oo[k]), (k, go[k], oo[k])
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("L", [16, 32, 64, 128, 256])
+def test_init_matches_oracle(L, layout):
+    R = R_OF_L[L]
+    print("case init L=%d layout=%s R=%d" % (L, layout, R), flush=True)
+    g = pa.Run(L, R, seed=7, run_id=3, layout=layout)
+    o = oracle.Run(L, R, seed=7, run_id=3)
+    o.init()
+    _same_population(g, o)
+    _same_obs(g.observables(), o.measure())
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("L", [16, 32, 64, 128, 256])
+@pytest.mark.parametrize("beta", [0.0, 1e-12, 0.2, 0.4406868, 0.9, 3.0])
+def test_sweep_matches_oracle(L, layout, beta):
+    R = R_OF_L[L]
+    nsw = 4 if L <= 64 else 2
+    print("case sweep L=%d layout=%s beta=%g" % (L, layout, beta), flush=True)
+    spins = inputs.mixed_spins(R, L, seed=L + 1)
+    g = pa.Run(L, R, seed=11, layout=layout)
+    g.upload_population(spins, step=3, sweeps=17, beta=beta)
+    o = oracle.Run(L, R, seed=11)
+    o.set_population(spins, step=3, sweeps=17, beta=beta)
+    _same_population(g, o)
+    g.sweep(nsw)
+    o.sweep(nsw)
+    _same_population(g, o)
+    assert g.state()["sweeps"] == o.sweeps == 17 + nsw
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_many_sweeps_exercise_ties(layout):
+    # ~5e5 random decisions: about eight reach the low 16 bits (ties)
+    L, R = 64, 9
+    print("case ties layout=%s" % layout, flush=True)
+    spins = inputs.random_spins(R, L, seed=5)
+    g = pa.Run(L, R, seed=3, layout=layout)
+    g.upload_population(spins, beta=0.6)
+    o = oracle.Run(L, R, seed=3)
+    o.set_population(spins, beta=0.6)
+    g.sweep(25)
+    o.sweep(25)
+    _same_population(g, o)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("L", [16, 64, 256])
+def test_resample_matches_oracle(L, layout):
+    R = {16: 1500, 64: 700, 256: 40}[L]
+    print("case resample L=%d layout=%s" % (L, layout), flush=True)
+    spins = inputs.mixed_spins(R, L, seed=3)
+    g = pa.Run(L, R, seed=5, layout=layout)
+    o = oracle.Run(L, R, seed=5)
+    g.upload_population(spins, step=4, sweeps=9, beta=0.3, lnZ=10.5)
+    o.set_population(spins, step=4, sweeps=9, beta=0.3, lnZ=10.5)
+    for beta in (0.3, 0.31, 0.45, 0.9):
+        gi = g.resample(beta)
+        oi = o.resample(beta)
+        assert gi["R_new"] == oi["R_new"]
+        assert gi["E_min"] == oi["E_min"]
+        assert gi["lnQ"] == oi["lnQ"]  # same FP64 operations in the same order
+        assert np.array_equal(g.download_counts(g.capacity), o.get_counts())
+        _same_population(g, o)
+        st = g.state()
+        assert st["lnZ"] == o.lnZ and st["step"] == o.step and st["beta"] == o.beta
+
+
+def _config1_trace(run, nsteps, theta, dbeta, measure):
+    trace = [measure()]
+    for i in range(1, nsteps + 1):
+        run.resample(i * dbeta)
+        run.sweep(theta)
+        trace.append(measure())
+    return trace
+
+
+@pytest.fixture(scope="module")
+def oracle_config1():
+    """L=16, R=1000, theta=10, dbeta=0.01, beta 0 -> 1 (100 steps), seed 1."""
+    o = oracle.Run(16, 1000, seed=1)
+    o.init()
+    trace = _config1_trace(o, 100, 10, 0.01, o.measure)
+    return o, trace
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_full_run_config1(layout, oracle_config1):
+    print("case config1 layout=%s" % layout, flush=True)
+    o, otrace = oracle_config1
+    g = pa.Run(16, 1000, seed=1, layout=layout)
+    gtrace = _config1_trace(g, 100, 10, 0.01, g.observables)
+    for go, oo in zip(gtrace, otrace):
+        _same_obs(go, oo)
+    _same_population(g, o)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_config2_full_size_sampled(layout):
+    """L=64, R=20000, theta=100: full-size init and resampling compared
+    element by element; the 100 sweeps compared on sampled replicas swept by
+    the oracle alone at their slots; invariants checked on every replica."""
+    L, R, theta = 64, 20000, 100
+    print("case config2 layout=%s" % layout, flush=True)
+    g = pa.Run(L, R, seed=1, layout=layout)
+    o = oracle.Run(L, R, seed=1)
+    o.init()
+    _same_population(g, o)
+    _same_obs(g.observables(), o.measure())
+    gi, oi = g.resample(0.005), o.resample(0.005)
+    assert gi == oi
+    assert np.array_equal(g.download_counts(g.capacity), o.get_counts())
+    _same_population(g, o)
+    pre, _, _ = o.get_population()
+    n = o.population
+    g.sweep(theta)
+    gs, gE, gM = g.download_population()
+    rng = np.random.default_rng(0)
+    slots = np.unique(np.concatenate([[0, 1, 63, 64, n - 1], rng.integers(0, n, 4)]))
+    so = oracle.Run(L, R, seed=1)
+    so.set_population(pre[slots], step=1, sweeps=0, beta=0.005)
+    so.set_slots(slots)
+    so.sweep(theta)
+    ss, sE, sM = so.get_population()
+    assert np.array_equal(ss, gs[slots]) and np.array_equal(sE, gE[slots]) and np.array_equal(sM, gM[slots])
+    # every replica: E and M are those of its spins
+    s = gs.astype(np.int32)
+    assert np.array_equal(-(s * (np.roll(s, -1, 2) + np.roll(s, -1, 1))).sum(axis=(1, 2)), gE)
+    assert np.array_equal(s.sum(axis=(1, 2)), gM)
+    obs = g.observables()
+    assert obs["sumE"] == int(gE.astype(np.int64).sum()) and obs["R"] == n
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_capacity_overflow_and_extinction(layout):
+    print("case capacity layout=%s" % layout, flush=True)
+    outcomes = []
+    for seed in range(1, 25):
+        # R = 100 from 3 equal replicas: R_new in 99..102, capacity 100
+        g = pa.Run(4 * 4, 100, seed=seed, capacity=100, layout=layout)
+        o = oracle.Run(16, 100, seed=seed, capacity=100)
+        s = np.ones((3, 16, 16), np.int8)
+        g.upload_population(s, beta=0.1)
+        o.set_population(s, beta=0.1)
+        try:
+            o.resample(0.2)
+            ok = True
+        except OverflowError:
+            ok = False
+        if ok:
+            g.resample(0.2)
+        else:
+            with pytest.raises(pa.CapacityError):
+                g.resample(0.2)
+            assert g.state()["step"] == 0 and g.state()["R"] == 3
+            # the run stays usable after the refusal
+            g.sweep(1)
+            o.sweep(1)
+        _same_population(g, o)
+        outcomes.append(ok)
+    assert not all(outcomes) and any(outcomes)
+    # extinction: R = 1 from two equal replicas survives with probability 3/4
+    ext = []
+    for seed in range(1, 25):
+        g = pa.Run(16, 1, seed=seed, capacity=8, layout=layout)
+        o = oracle.Run(16, 1, seed=seed, capacity=8)
+        s = np.ones((2, 16, 16), np.int8)
+        g.upload_population(s, beta=0.1)
+        o.set_population(s, beta=0.1)
+        try:
+            o.resample(0.2)
+            dead = False
+        except ArithmeticError:
+            dead = True
+        if dead:
+            with pytest.raises(pa.ExtinctError):
+                g.resample(0.2)
+            assert g.state()["R"] == 2
+        else:
+            g.resample(0.2)
+        _same_population(g, o)
+        ext.append(dead)
+    assert any(ext) and not all(ext)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_adaptive_run_and_reweighting(layout):
+    """Adaptive steps (alpha* = 0.85) with multi-histogram reweighting."""
+    print("case adaptive layout=%s" % layout, flush=True)
+    L, R, theta = 16, 2000, 5
+    g = pa.Run(L, R, seed=9, layout=layout, mhr=True)
+    o = oracle.Run(L, R, seed=9)
+    o.init()
+    _same_obs(g.observables(), o.measure())
+    steps = 0
+    while o.beta < 1.0:
+        bo = o.adapt_beta(0.85, 1.0)
+        bg = g.adapt_beta(0.85, 1.0)
+        assert bg == bo
+        assert g.alpha(bo) == o.alpha(bo)
+        assert g.resample(bg) == o.resample(bo)
+        g.sweep(theta)
+        o.sweep(theta)
+        _same_obs(g.observables(), o.measure())
+        steps += 1
+    assert steps > 5
+    _same_population(g, o)
+    betas = np.linspace(0.0, 1.2, 61)
+    for go, oo in zip(g.reweight(betas), o.reweight(betas)):
+        for k in ("e", "C", "abs_m", "m2", "m4", "betaF_per_N", "S_per_N"):
+            assert _close(go[k], oo[k], 1e-12), (k, go["beta"], go[k], oo[k])
+
+
+def test_runs_are_deterministic_and_keyed():
+    print("case determinism", flush=True)
+    a = pa.Run(32, 100, seed=4)
+    b = pa.Run(32, 100, seed=4)
+    c = pa.Run(32, 100, seed=4, run_id=1)
+    for r in (a, b, c):
+        r.resample(0.3)
+        r.sweep(3)
+    sa, sb, sc = (r.download_population()[0] for r in (a, b, c))
+    assert np.array_equal(sa, sb)
+    assert not np.array_equal(sa, sc)
+
+
+def test_argument_errors_on_device_runs():
+    g = pa.Run(16, 10, seed=1)
+    with pytest.raises(pa.PaError):
+        g.sweep(-1)
+    with pytest.raises(pa.PaError):
+        g.resample(-0.1)  # below the current beta
+    with pytest.raises(pa.PaError):
+        g.adapt_beta(1.5, 1.0)
+    with pytest.raises(pa.PaError):
+        g.reweight([0.1])  # run without the multi-histogram flag
+    with pytest.raises(pa.PaError):
+        g.upload_population(np.zeros((2, 16, 16), np.int8))  # spins must be +-1
+    g.sweep(0)
+    assert g.state()["sweeps"] == 0
