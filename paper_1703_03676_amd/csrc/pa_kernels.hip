@@ -33,6 +33,12 @@ struct U4 {
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
 // multiplies, xor of the high halves with the other words and the round key.
+// The three-way xors are single v_bitop3 instructions (truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                        uint32_t k1)
 {
@@ -40,8 +46,8 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)kM0 * c0;
         const uint64_t p1 = (uint64_t)kM1 * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -170,6 +176,33 @@ struct Neighbours {
     }
 };
 
+// One bit plane of the bit-serial comparison "uniform < threshold", high bit
+// first, for the sites still tied.  k = 2 sites (cls1) compare against T_2,
+// k = 4 sites against T_4; `tb` holds the two threshold bits of this plane
+// (bit 1: T_2, bit 0: T_4) and is uniform, so each case is straight-line code.
+//   threshold bit 1: plane bit 0 -> below (accept), plane bit 1 -> still tied
+//   threshold bit 0: plane bit 1 -> above (reject), plane bit 0 -> still tied
+__device__ __forceinline__ void compare_plane(uint32_t x, uint32_t tb, uint32_t cls1, uint32_t& eq, uint32_t& acc)
+{
+    switch (tb) {
+    case 0:
+        eq &= ~x;
+        break;
+    case 3:
+        acc |= eq & ~x;
+        eq &= x;
+        break;
+    case 2:  // T_2 bit set, T_4 bit clear
+        acc |= eq & cls1 & ~x;
+        eq &= ~(x ^ cls1);
+        break;
+    default:  // T_4 bit set, T_2 bit clear
+        acc |= eq & ~cls1 & ~x;
+        eq &= x ^ cls1;
+        break;
+    }
+}
+
 // Metropolis acceptance mask of one 32-site word.  A site flips if at least two
 // of its four neighbours are anti-aligned (k = s h <= 0), else if its uniform
 // x (high 16 bits from the bit planes, low 16 bits drawn on a tie) is below
@@ -181,42 +214,31 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_
     const uint32_t o12 = d1 | d2, a12 = d1 & d2, o34 = d3 | d4, a34 = d3 & d4;
     const uint32_t ge2 = a12 | a34 | (o12 & o34);
     const uint32_t any = o12 | o34;
-    uint32_t eq2 = any & ~ge2;   // k = 2 sites still tied with T_2 on the planes seen so far
-    uint32_t eq4 = ~any;         // k = 4 sites still tied with T_4
+    const uint32_t cls1 = any & ~ge2;  // k = 2
+    uint32_t eq = ~ge2;                // sites still tied with their threshold
     uint32_t acc = ge2;
-    if (a.t2h > 0xFFFFu) {       // T_2 = 2^32: always accepted
-        acc |= eq2;
-        eq2 = 0;
+    if (a.t2h > 0xFFFFu) {             // T_2 = 2^32: always accepted
+        acc |= cls1;
+        eq &= ~cls1;
     }
     if (a.t4h > 0xFFFFu) {
-        acc |= eq4;
-        eq4 = 0;
+        acc |= ~any;
+        eq &= any;
     }
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
-        if (!__any((eq2 | eq4) != 0u)) break;
+        if (!__any(eq != 0u)) break;
         const U4 P = philox10(4u * v + (uint32_t)kk, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
         const uint32_t pl[4] = {P.x, P.y, P.z, P.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int bit = 15 - (4 * kk + q);
-            const uint32_t x = pl[q];
-            if ((a.t2h >> bit) & 1u) {
-                acc |= eq2 & ~x;
-                eq2 &= x;
-            } else {
-                eq2 &= ~x;
-            }
-            if ((a.t4h >> bit) & 1u) {
-                acc |= eq4 & ~x;
-                eq4 &= x;
-            } else {
-                eq4 &= ~x;
-            }
+            const uint32_t tb = (((a.t2h >> bit) & 1u) << 1) | ((a.t4h >> bit) & 1u);
+            compare_plane(pl[q], tb, cls1, eq, acc);
         }
     }
-    uint32_t tie = eq2 | eq4;
-    if (__any(tie != 0u)) {
+    if (__any(eq != 0u)) {
+        uint32_t tie = eq;
         while (tie) {
             const int b = __builtin_ctz(tie);
             tie &= tie - 1u;
@@ -224,7 +246,7 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_
             const U4 P = philox10(q >> 3, ctr1, j, kStreamSweepLow, a.key0, a.key1);
             const uint32_t word = pick(P, (q >> 1) & 3u);
             const uint32_t lo = (q & 1u) ? (word & 0xFFFFu) : (word >> 16);
-            const uint32_t tl = ((eq2 >> b) & 1u) ? a.t2l : a.t4l;
+            const uint32_t tl = ((cls1 >> b) & 1u) ? a.t2l : a.t4l;
             if (lo < tl) acc |= 1u << b;
         }
     }
