@@ -182,6 +182,72 @@ pa_status pa_upload_population(pa_run* r, int32_t R_cur, const int8_t* spins, in
  * number of parents; counts must hold capacity entries. */
 pa_status pa_download_counts(pa_run* r, uint32_t* counts, int32_t* n);
 
+/* ---- Batched runs: many independent PA runs advanced together. ----------
+ * Every run has its own parameters (L, R, seed, run_id, layout, flags) and
+ * schedule.  One pa_batch_step advances every unfinished run by one
+ * temperature step (choose beta_{i+1}, resample, theta sweeps, measure) with
+ * one batched launch per phase, replayed from a HIP graph, and one host
+ * synchronisation for the whole batch.  Each run follows exactly the same
+ * arithmetic and random streams as a single run with the same parameters and
+ * schedule, so its results are bit-identical to that run's. */
+
+typedef enum {
+    PA_STEP_FIXED = 0,     /* beta_i = i * dbeta, last step clamped to beta_f (Sec. 2.1) */
+    PA_STEP_ADAPTIVE = 1,  /* histogram-overlap bisection to alpha_star (Sec. 2.3) */
+    PA_STEP_LEARNED = 2    /* learned proposal accepted by the exact overlap test, else bisection */
+} pa_step_mode;
+
+typedef struct {
+    double beta_f;       /* final inverse temperature (> 0) */
+    double dbeta;        /* fixed step size (PA_STEP_FIXED) */
+    double alpha_star;   /* overlap target in (0,1) (adaptive and learned modes) */
+    double alpha_tol;    /* learned mode: accept a proposal if |alpha - alpha_star| <= alpha_tol */
+    int32_t theta;       /* sweeps per temperature step (>= 0) */
+    int32_t mode;        /* pa_step_mode */
+} pa_schedule;
+
+typedef struct pa_batch pa_batch;  /* opaque host handle */
+
+/* Device workspace for nruns runs; 0 if any parameter set is invalid. */
+size_t pa_batch_workspace_bytes(const pa_params* runs, int32_t nruns);
+
+/* Start nruns runs at beta_0 = 0 (Sec. 2.1 step 1) and measure them once.
+ * `hip_stream` may be NULL: the batch then creates its own stream (graph
+ * capture needs a non-null stream).  Errors: PA_EINVAL (invalid run
+ * parameters or schedule, nruns < 1), PA_ENOMEM, PA_EHIP. */
+pa_status pa_batch_init(const pa_params* runs, const pa_schedule* sched, int32_t nruns, void* d_workspace,
+                        size_t bytes, void* hip_stream, pa_batch** out);
+
+/* One temperature step of every unfinished run.  *n_active (may be NULL)
+ * receives the number of runs still below beta_f afterwards.  A run whose
+ * step fails (capacity, extinction, no adaptive step) stops with its state
+ * at the last good step; pa_batch_run_status reports why.  Errors:
+ * PA_ESTATE, PA_EHIP. */
+pa_status pa_batch_step(pa_batch* b, int32_t* n_active);
+
+/* Steps until every run has reached beta_f or stopped. */
+pa_status pa_batch_run(pa_batch* b);
+
+/* Status of one run: PA_OK while running or finished, else the error that
+ * stopped it (PA_ECAPACITY, PA_EEXTINCT, PA_EINVAL for a failed adaptive step). */
+pa_status pa_batch_run_status(const pa_batch* b, int32_t run);
+
+/* Counters of one run. */
+pa_status pa_batch_state(const pa_batch* b, int32_t run, pa_state_info* out);
+
+/* Observables of one run at every temperature so far (index 0 is beta_0 = 0):
+ * copies min(cap, count) entries and stores the count in *n. */
+pa_status pa_batch_history(const pa_batch* b, int32_t run, pa_obs* out, int32_t cap, int32_t* n);
+
+/* Multi-histogram reweighting of one run (requires PA_FLAG_MHR on that run). */
+pa_status pa_batch_reweight(pa_batch* b, int32_t run, const double* betas, int32_t nb, pa_obs* out);
+
+/* Population of one run as int8 +-1 row-major spins and E, M (test hook). */
+pa_status pa_batch_download_population(pa_batch* b, int32_t run, int8_t* spins, int32_t* E, int32_t* M);
+
+/* Release the batch handle (the caller frees the workspace). */
+pa_status pa_batch_free(pa_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -68,6 +68,15 @@ class StateInfo(ctypes.Structure):
                 ("beta", ctypes.c_double), ("lnZ", ctypes.c_double)]
 
 
+class Schedule(ctypes.Structure):
+    _fields_ = [("beta_f", ctypes.c_double), ("dbeta", ctypes.c_double), ("alpha_star", ctypes.c_double),
+                ("alpha_tol", ctypes.c_double), ("theta", ctypes.c_int32), ("mode", ctypes.c_int32)]
+
+
+PA_STEP_FIXED, PA_STEP_ADAPTIVE, PA_STEP_LEARNED = 0, 1, 2
+STEP_MODES = {"fixed": PA_STEP_FIXED, "adaptive": PA_STEP_ADAPTIVE, "learned": PA_STEP_LEARNED}
+
+
 # Every symbol declared in include/pa.h, with its ctypes signature.
 _P = ctypes.POINTER
 _vp = ctypes.c_void_p
@@ -88,6 +97,16 @@ SIGNATURES = {
     "pa_upload_population": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, ctypes.c_int32, ctypes.c_uint64,
                                             ctypes.c_double, ctypes.c_double]),
     "pa_download_counts": (ctypes.c_int, [_vp, _vp, _P(ctypes.c_int32)]),
+    "pa_batch_workspace_bytes": (ctypes.c_size_t, [_P(Params), ctypes.c_int32]),
+    "pa_batch_init": (ctypes.c_int, [_P(Params), _P(Schedule), ctypes.c_int32, _vp, ctypes.c_size_t, _vp, _P(_vp)]),
+    "pa_batch_step": (ctypes.c_int, [_vp, _P(ctypes.c_int32)]),
+    "pa_batch_run": (ctypes.c_int, [_vp]),
+    "pa_batch_run_status": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pa_batch_state": (ctypes.c_int, [_vp, ctypes.c_int32, _P(StateInfo)]),
+    "pa_batch_history": (ctypes.c_int, [_vp, ctypes.c_int32, _P(Obs), ctypes.c_int32, _P(ctypes.c_int32)]),
+    "pa_batch_reweight": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_double), ctypes.c_int32, _P(Obs)]),
+    "pa_batch_download_population": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp]),
+    "pa_batch_free": (ctypes.c_int, [_vp]),
 }
 
 _lib = None
@@ -227,6 +246,90 @@ class Run:
         n = ctypes.c_int32()
         _check(lib().pa_download_counts(self.h, _ptr(buf), ctypes.byref(n)), self.h)
         return buf[: n.value].copy()
+
+
+def make_schedule(beta_f=1.0, dbeta=0.0, alpha_star=0.0, alpha_tol=0.0, theta=1, mode="fixed"):
+    return Schedule(beta_f=float(beta_f), dbeta=float(dbeta), alpha_star=float(alpha_star),
+                    alpha_tol=float(alpha_tol), theta=int(theta),
+                    mode=STEP_MODES[mode] if isinstance(mode, str) else int(mode))
+
+
+class Batch:
+    """Many independent PA runs advanced together (one graph replay per step).
+
+    runs: list of dicts with keys L, R, seed and optional run_id, capacity,
+    layout, mhr.  schedules: list of dicts for make_schedule (or one dict for
+    all runs)."""
+
+    def __init__(self, runs, schedules, stream=None, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU available: libpa runs on the GPU only")
+        n = len(runs)
+        if isinstance(schedules, dict):
+            schedules = [schedules] * n
+        self.specs = [dict(r) for r in runs]
+        self.params = (Params * n)(*[make_params(r["L"], r["R"], r["seed"], r.get("run_id", 0), r.get("capacity", 0),
+                                                 r.get("layout", "bits"), r.get("mhr", False)) for r in runs])
+        self.sched = (Schedule * n)(*[make_schedule(**sc) for sc in schedules])
+        nbytes = lib().pa_batch_workspace_bytes(self.params, n)
+        if nbytes == 0:
+            raise PaError(PA_EINVAL, "invalid run parameters")
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        sp = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check(lib().pa_batch_init(self.params, self.sched, n, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                   sp, ctypes.byref(h)))
+        self.h = h
+        self.n = n
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pa_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def step(self):
+        n = ctypes.c_int32()
+        _check(lib().pa_batch_step(self.h, ctypes.byref(n)))
+        return n.value
+
+    def run(self):
+        _check(lib().pa_batch_run(self.h))
+
+    def status(self, run):
+        return lib().pa_batch_run_status(self.h, int(run))
+
+    def state(self, run):
+        s = StateInfo()
+        _check(lib().pa_batch_state(self.h, int(run), ctypes.byref(s)))
+        return {"R": s.R, "step": s.step, "sweeps": s.sweeps, "beta": s.beta, "lnZ": s.lnZ}
+
+    def history(self, run):
+        n = ctypes.c_int32()
+        _check(lib().pa_batch_history(self.h, int(run), None, 0, ctypes.byref(n)))
+        out = (Obs * max(n.value, 1))()
+        _check(lib().pa_batch_history(self.h, int(run), out, n.value, ctypes.byref(n)))
+        return [out[k].as_dict() for k in range(n.value)]
+
+    def reweight(self, run, betas):
+        betas = np.ascontiguousarray(betas, dtype=np.float64)
+        out = (Obs * max(len(betas), 1))()
+        _check(lib().pa_batch_reweight(self.h, int(run), betas.ctypes.data_as(_P(ctypes.c_double)), len(betas), out))
+        return [out[k].as_dict() for k in range(len(betas))]
+
+    def download_population(self, run):
+        L = self.specs[run]["L"]
+        n = self.state(run)["R"]
+        s = np.empty((n, L, L), np.int8)
+        E = np.empty(n, np.int32)
+        M = np.empty(n, np.int32)
+        _check(lib().pa_batch_download_population(self.h, int(run), _ptr(s), _ptr(E), _ptr(M)))
+        return s, E, M
 
 
 def default_capacity(R):

@@ -16,10 +16,12 @@
 #include <vector>
 
 #include "pa.h"
+#include "pa_host.h"
 #include "pa_internal.h"
 
 using pa::DevMhr;
 using pa::DevStats;
+namespace host = pa::host;
 
 namespace {
 
@@ -127,20 +129,6 @@ pa_status usable(const pa_run* r)
     return r->broken ? PA_ESTATE : PA_OK;
 }
 
-int32_t energy_of_bin(const pa_run* r, int b) { return 4 * b - 2 * r->N; }
-
-// Metropolis thresholds ceil(2^32 exp(-2 beta k)) for k = 2 and k = 4, split
-// into the high part (compared bit-plane by bit-plane) and the low 16 bits.
-void thresholds(double beta, pa::SweepArgs* a)
-{
-    const uint64_t t2 = (uint64_t)std::ceil(std::ldexp(std::exp(-4.0 * beta), 32));
-    const uint64_t t4 = (uint64_t)std::ceil(std::ldexp(std::exp(-8.0 * beta), 32));
-    a->t2h = (uint32_t)(t2 >> 16);
-    a->t2l = (uint32_t)(t2 & 0xFFFFu);
-    a->t4h = (uint32_t)(t4 >> 16);
-    a->t4l = (uint32_t)(t4 & 0xFFFFu);
-}
-
 void key_of(const pa_run* r, uint32_t* k0, uint32_t* k1)
 {
     *k0 = (uint32_t)r->p.seed;
@@ -158,7 +146,7 @@ pa_status launch_sweeps(pa_run* r, int32_t nsweeps, bool init)
     a.nsweeps = nsweeps;
     a.g0 = (uint32_t)r->sweeps;
     key_of(r, &a.key0, &a.key1);
-    thresholds(r->beta, &a);
+    host::thresholds(r->beta, &a.t2h, &a.t2l, &a.t4h, &a.t4l);
     a.init = init ? 1 : 0;
     HIPCHK(pa::launch_sweep(r->L, r->p.layout, a, r->stream));
     return PA_OK;
@@ -187,46 +175,7 @@ pa_status refresh_stats(pa_run* r, bool record)
     return PA_OK;
 }
 
-// W = sum over occupied bins (ascending) of n(b) w(b), w(b) = exp(-dbeta (E_b - E_min)).
-double weight_sum(const pa_run* r, int bmin, int bmax, double dbeta, std::vector<double>* w)
-{
-    const int32_t Emin = energy_of_bin(r, bmin);
-    double W = 0.0;
-    for (int b = bmin; b <= bmax; ++b) {
-        const uint32_t n = r->h_hist[b];
-        if (n == 0) continue;
-        const double d = (double)(energy_of_bin(r, b) - Emin);
-        const double wb = std::exp(-(dbeta * d));
-        if (w) (*w)[b - bmin] = wb;
-        W += (double)n * wb;
-    }
-    return W;
-}
-
-int bin_lo(const pa_run* r) { return (r->h_stats.emin + 2 * r->N) / 4; }
-int bin_hi(const pa_run* r) { return (r->h_stats.emax + 2 * r->N) / 4; }
-
-// Histogram overlap alpha(beta_i, beta') (Sec. 2.3) over energy bins.
-double overlap(const pa_run* r, double beta_prime)
-{
-    const int bmin = bin_lo(r), bmax = bin_hi(r);
-    std::vector<double> w((size_t)(bmax - bmin + 1));
-    const double W = weight_sum(r, bmin, bmax, beta_prime - r->beta, &w);
-    double acc = 0.0;
-    for (int b = bmin; b <= bmax; ++b) {
-        const uint32_t n = r->h_hist[b];
-        if (n == 0) continue;
-        const double tau = ((double)r->p.R * w[b - bmin]) / W;
-        acc += (double)n * (tau < 1.0 ? tau : 1.0);
-    }
-    return acc / (double)r->R_cur;
-}
-
-double u128_to_double(uint64_t lo, uint64_t hi)
-{
-    const unsigned __int128 v = ((unsigned __int128)hi << 64) | lo;
-    return (double)v;
-}
+host::Hist window(const pa_run* r) { return host::hist_window(r->h_hist.data(), r->h_stats, r->N); }
 
 }  // namespace
 
@@ -341,24 +290,12 @@ pa_status pa_resample(pa_run* r, double beta_next, pa_resample_info* out)
     if (st != PA_OK) return st;
 
     // Eq. (Q) with the E_min shift, and the tables of Eq. (resampling factors).
-    const int bmin = bin_lo(r), bmax = bin_hi(r), nwin = bmax - bmin + 1;
-    const double dbeta = beta_next - r->beta;
-    std::vector<double> w((size_t)nwin);
-    const double W = weight_sum(r, bmin, bmax, dbeta, &w);
-    const int32_t Emin = energy_of_bin(r, bmin);
-    const double lnQ = std::log(W) - std::log((double)r->R_cur) - dbeta * (double)Emin;
+    const host::Hist h = window(r);
+    const int bmin = h.bmin, nwin = h.bmax - h.bmin + 1;
+    const int32_t Emin = h.energy(bmin);
     uint32_t* tab = (uint32_t*)r->pinned;
-    for (int b = bmin; b <= bmax; ++b) {
-        uint32_t base = 0, thr = 0;
-        if (r->h_hist[b] != 0) {
-            const double tau = ((double)r->p.R * w[b - bmin]) / W;
-            const double fl = std::floor(tau);
-            base = (uint32_t)fl;
-            thr = (uint32_t)std::floor(std::ldexp(tau - fl, 32));
-        }
-        tab[2 * (b - bmin)] = base;
-        tab[2 * (b - bmin) + 1] = thr;
-    }
+    std::vector<double> w;
+    const double lnQ = host::resample_tables(h, r->p.R, r->R_cur, beta_next - r->beta, tab, w);
     HIPCHK(hipMemcpyAsync(r->tbl, tab, (size_t)nwin * 8, hipMemcpyHostToDevice, r->stream));
 
     uint32_t k0, k1;
@@ -404,7 +341,8 @@ pa_status pa_alpha(pa_run* r, double beta_prime, double* alpha)
     if (!alpha || !std::isfinite(beta_prime)) return PA_EINVAL;
     st = refresh_stats(r, false);
     if (st != PA_OK) return st;
-    *alpha = overlap(r, beta_prime);
+    std::vector<double> w;
+    *alpha = host::overlap(window(r), r->p.R, r->R_cur, beta_prime - r->beta, w);
     return PA_OK;
 }
 
@@ -416,23 +354,9 @@ pa_status pa_adapt_beta(pa_run* r, double alpha_star, double beta_f, double* bet
         return PA_EINVAL;
     st = refresh_stats(r, false);
     if (st != PA_OK) return st;
-    const double a_f = overlap(r, beta_f);
-    if (a_f >= alpha_star) {
-        *beta_next = beta_f;
-        if (alpha_at_next) *alpha_at_next = a_f;
-        return PA_OK;
-    }
-    double lo = r->beta, hi = beta_f;
-    for (int it = 0; it < 50; ++it) {
-        const double mid = lo + 0.5 * (hi - lo);
-        if (overlap(r, mid) >= alpha_star)
-            lo = mid;
-        else
-            hi = mid;
-    }
-    if (lo == r->beta) return PA_EINVAL;
-    *beta_next = lo;
-    if (alpha_at_next) *alpha_at_next = overlap(r, lo);
+    std::vector<double> w;
+    if (!host::adapt_beta(window(r), r->p.R, r->R_cur, r->beta, beta_f, alpha_star, beta_next, alpha_at_next, w))
+        return PA_EINVAL;
     return PA_OK;
 }
 
@@ -444,28 +368,9 @@ pa_status pa_observables(pa_run* r, pa_obs* o)
     const bool record = (r->p.flags & PA_FLAG_MHR) != 0;
     st = refresh_stats(r, record);
     if (st != PA_OK) return st;
-    const DevStats& s = r->h_stats;
-    const int64_t sE = (int64_t)s.sumE, sE2 = (int64_t)s.sumE2;
-    const double N = (double)r->N, R = (double)r->R_cur, beta = r->beta;
-    const __int128 D = (__int128)r->R_cur * (__int128)sE2 - (__int128)sE * (__int128)sE;
-    o->beta = beta;
-    o->e = (double)sE / (R * N);
-    o->C = (beta * beta * (double)D) / (N * R * R);
-    o->abs_m = (double)(int64_t)s.sumAbsM / (R * N);
-    o->m2 = (double)(int64_t)s.sumM2 / (R * N * N);
-    o->m4 = u128_to_double(s.sumM4_lo, s.sumM4_hi) / (R * N * N * N * N);
-    o->betaF_per_N = -r->lnZ / N;
-    o->S_per_N = beta * o->e + r->lnZ / N;
-    o->lnQ = r->lnQ_last;
-    o->R = r->R_cur;
-    o->sumE = sE;
-    o->sumE2 = sE2;
-    o->sumAbsM = (int64_t)s.sumAbsM;
-    o->sumM2 = (int64_t)s.sumM2;
-    o->sumM4_lo = s.sumM4_lo;
-    o->sumM4_hi = s.sumM4_hi;
+    host::observables(r->h_stats, r->R_cur, r->N, r->beta, r->lnZ, r->lnQ_last, o);
     if (record) {
-        r->m_beta.push_back(beta);
+        r->m_beta.push_back(r->beta);
         r->m_lnZ.push_back(r->lnZ);
         r->m_R.push_back(r->R_cur);
     }
@@ -483,66 +388,7 @@ pa_status pa_reweight(pa_run* r, const double* betas, int32_t nb, pa_obs* out)
     HIPCHK(hipMemcpyAsync(acc.data(), r->mhr.H, acc.size() * 8, hipMemcpyDeviceToHost, r->stream));
     HIPCHK(hipStreamSynchronize(r->stream));
     const uint64_t* H = acc.data();
-    const uint64_t* SA = H + nbins;
-    const uint64_t* SM2 = H + 2 * nbins;
-    const uint64_t* SM4 = H + 3 * nbins;
-    const double N = (double)r->N;
-    const size_t nm = r->m_beta.size();
-
-    // ln Omega(E) = ln H(E) - ln sum_i R_i exp(-ln Z_i - beta_i E)   (Sec. 2.4)
-    std::vector<double> lnOmega(nbins, 0.0), lw(nbins, 0.0), terms(nm);
-    for (size_t b = 0; b < nbins; ++b) {
-        if (H[b] == 0) continue;
-        const double E = (double)energy_of_bin(r, (int)b);
-        double mx = -INFINITY;
-        for (size_t i = 0; i < nm; ++i) {
-            terms[i] = std::log((double)r->m_R[i]) - r->m_lnZ[i] - r->m_beta[i] * E;
-            if (terms[i] > mx) mx = terms[i];
-        }
-        double s = 0.0;
-        for (size_t i = 0; i < nm; ++i) s += std::exp(terms[i] - mx);
-        lnOmega[b] = std::log((double)H[b]) - (mx + std::log(s));
-    }
-    for (int32_t k = 0; k < nb; ++k) {
-        const double beta = betas[k];
-        double mx = -INFINITY;
-        for (size_t b = 0; b < nbins; ++b) {
-            if (H[b] == 0) continue;
-            lw[b] = lnOmega[b] - beta * (double)energy_of_bin(r, (int)b);
-            if (lw[b] > mx) mx = lw[b];
-        }
-        double s = 0.0;
-        for (size_t b = 0; b < nbins; ++b)
-            if (H[b] != 0) s += std::exp(lw[b] - mx);
-        const double lnZ = mx + std::log(s);
-        double mE = 0.0, mA = 0.0, mM2 = 0.0, mM4 = 0.0;
-        for (size_t b = 0; b < nbins; ++b) {
-            if (H[b] == 0) continue;
-            const double p = std::exp(lw[b] - lnZ);
-            const double h = (double)H[b];
-            mE += p * (double)energy_of_bin(r, (int)b);
-            mA += p * ((double)SA[b] / h);
-            mM2 += p * ((double)SM2[b] / h);
-            mM4 += p * (u128_to_double(SM4[2 * b], SM4[2 * b + 1]) / h);
-        }
-        double var = 0.0;
-        for (size_t b = 0; b < nbins; ++b) {
-            if (H[b] == 0) continue;
-            const double p = std::exp(lw[b] - lnZ);
-            const double d = (double)energy_of_bin(r, (int)b) - mE;
-            var += p * d * d;
-        }
-        pa_obs* o = &out[k];
-        std::memset(o, 0, sizeof(*o));
-        o->beta = beta;
-        o->e = mE / N;
-        o->C = beta * beta * var / N;
-        o->abs_m = mA / N;
-        o->m2 = mM2 / (N * N);
-        o->m4 = mM4 / (N * N * N * N);
-        o->betaF_per_N = -lnZ / N;
-        o->S_per_N = beta * o->e + lnZ / N;
-    }
+    host::reweight(r->N, H, H + nbins, H + 2 * nbins, H + 3 * nbins, r->m_beta, r->m_lnZ, r->m_R, betas, nb, out);
     return PA_OK;
 }
 
@@ -579,17 +425,7 @@ pa_status pa_download_population(pa_run* r, int8_t* spins, int32_t* E, int32_t* 
             std::vector<uint32_t> words(n * (size_t)r->N / 32);
             HIPCHK(hipMemcpyAsync(words.data(), r->spin[r->cur], words.size() * 4, hipMemcpyDeviceToHost, r->stream));
             HIPCHK(hipStreamSynchronize(r->stream));
-            const int L = r->L, half = r->N / 2, hw = L / 2;
-            for (size_t j = 0; j < n; ++j) {
-                const uint32_t* wj = words.data() + j * (size_t)(r->N / 32);
-                int8_t* sj = spins + j * (size_t)r->N;
-                for (int c = 0; c < 2; ++c)
-                    for (int q = 0; q < half; ++q) {
-                        const int y = q / hw, x = 2 * (q % hw) + ((y + c) & 1);
-                        const uint32_t bit = (wj[c * (half / 32) + (q >> 5)] >> (q & 31)) & 1u;
-                        sj[y * L + x] = bit ? -1 : 1;
-                    }
-            }
+            host::bits_to_int8(words.data(), r->L, n, spins);
         }
     }
     HIPCHK(hipStreamSynchronize(r->stream));
@@ -612,16 +448,7 @@ pa_status pa_upload_population(pa_run* r, int32_t R_cur, const int8_t* spins, in
         HIPCHK(hipStreamSynchronize(r->stream));
     } else {
         std::vector<uint32_t> words(n * N / 32, 0u);
-        const int L = r->L, half = r->N / 2, hw = L / 2;
-        for (size_t j = 0; j < n; ++j) {
-            uint32_t* wj = words.data() + j * (N / 32);
-            const int8_t* sj = spins + j * N;
-            for (int c = 0; c < 2; ++c)
-                for (int q = 0; q < half; ++q) {
-                    const int y = q / hw, x = 2 * (q % hw) + ((y + c) & 1);
-                    if (sj[y * L + x] < 0) wj[c * (half / 32) + (q >> 5)] |= 1u << (q & 31);
-                }
-        }
+        host::int8_to_bits(spins, r->L, n, words.data());
         HIPCHK(hipMemcpyAsync(r->spin[r->cur], words.data(), words.size() * 4, hipMemcpyHostToDevice, r->stream));
         HIPCHK(hipStreamSynchronize(r->stream));
     }

@@ -1,0 +1,1139 @@
+// Batched population annealing: many independent runs (each with its own L,
+// R, seed, spin store and schedule) advanced one temperature step at a time.
+//
+// One step of the whole batch:
+//   host    per run, in a thread pool: next beta (fixed, adaptive bisection or
+//           learned proposal + exact overlap test), FP64 copy-count tables of
+//           Eq. (resampling factors), Metropolis thresholds
+//   copy    one upload of every run's step descriptor and tables
+//   graph   counts -> per-run scan -> parent scatter -> replica copy -> sweep
+//           (one launch per lattice size and store) -> statistics -> one
+//           download of every run's statistics block and energy histogram
+//   host    commit each run (ln Z += ln Q, observables of Eq. (observables))
+// The device part is captured once in a HIP graph and replayed every step.
+// Kernels read each run's step descriptor and its device-side population
+// size, so launch shapes stay fixed while R_i changes.  A run whose resampling
+// would exceed its capacity or die out is flagged on the device; its copy and
+// sweep are skipped and its state stays at the last good step.
+//
+// Launch shapes of the sweep (waves per block) are chosen per (lattice size,
+// store) by timing the candidates on the batch's own spare buffers at start-up.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "pa.h"
+#include "pa_device.h"
+#include "pa_host.h"
+
+namespace pa {
+namespace batch {
+
+using namespace pa::dev;
+
+struct RunDev {
+    uint8_t* spin[2];
+    int32_t* E[2];
+    int32_t* M[2];
+    uint32_t* counts;
+    uint32_t* parent;
+    uint32_t* bsum;
+    DevStats* stats;  // followed by the energy histogram
+    uint32_t* hist;
+    DevMhr mhr;
+    int32_t L, N, nbins, capacity, layout, R;
+    uint32_t rep_bytes;
+    uint32_t key0, key1;
+};
+
+struct StepDev {
+    int32_t active;    // the run takes part in this step
+    int32_t resample;  // resample before the sweeps
+    int32_t init;      // draw the initial state instead of loading spins
+    int32_t record;    // add this measurement to the multi-histogram accumulators
+    int32_t cur;       // buffer holding the parents
+    int32_t n_parent;  // R_{i-1}
+    uint32_t step;     // resampling index i (RESAMPLE stream counter)
+    uint32_t g0;       // sweep counter of the first sweep of this step
+    int32_t nsweeps;
+    uint32_t t2h, t2l, t4h, t4l;
+    int32_t bmin, nwin;
+    uint32_t tbl_off;  // offset in u32 of this run's tables in the table area
+};
+
+struct ResultDev {
+    uint32_t r_new;  // sum of the copy counts
+    uint32_t err;    // 0 ok, 1 capacity exceeded, 2 no replica left
+};
+
+struct Item {
+    int32_t run, blk;
+};
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+// The buffer and population size the sweep and the statistics work on.
+__device__ __forceinline__ bool post_resample(const StepDev& st, const ResultDev& rs, int* buf, int* n)
+{
+    if (st.resample) {
+        if (rs.err) {
+            *buf = st.cur;
+            *n = st.n_parent;
+            return false;
+        }
+        *buf = st.cur ^ 1;
+        *n = (int)rs.r_new;
+        return true;
+    }
+    *buf = st.cur;
+    *n = st.n_parent;
+    return true;
+}
+
+__global__ __launch_bounds__(kBlock) void b_counts(const Item* __restrict__ items, const RunDev* __restrict__ runs,
+                                                   const StepDev* __restrict__ steps, const uint32_t* __restrict__ tbl)
+{
+    const Item it = items[blockIdx.x];
+    const StepDev st = steps[it.run];
+    if (!st.active || !st.resample || it.blk * kBlock >= st.n_parent) return;  // uniform per block
+    const RunDev& rd = runs[it.run];
+    const int j = it.blk * kBlock + (int)threadIdx.x;
+    uint32_t c = 0;
+    if (j < st.n_parent) {
+        const int b = ((rd.E[st.cur][j] + 2 * rd.N) >> 2) - st.bmin;
+        const uint32_t x = pick(philox10((uint32_t)j >> 2, st.step, 0u, kStreamResample, rd.key0, rd.key1),
+                                (uint32_t)j & 3u);
+        if (b >= 0 && b < st.nwin) {
+            const uint32_t base = tbl[st.tbl_off + 2 * b], thr = tbl[st.tbl_off + 2 * b + 1];
+            c = base + (x <= thr ? 1u : 0u);
+        }
+        rd.counts[j] = c;
+    }
+    uint32_t total;
+    block_exclusive_scan(c, &total);
+    if (threadIdx.x == 0) rd.bsum[it.blk] = total;
+}
+
+// One block per run: exclusive scan of its block sums, total and status.
+__global__ __launch_bounds__(1024) void b_scan(const RunDev* __restrict__ runs, const StepDev* __restrict__ steps,
+                                               ResultDev* __restrict__ res)
+{
+    __shared__ uint32_t part[1024];
+    const StepDev st = steps[blockIdx.x];
+    if (!st.active || !st.resample) return;
+    uint32_t* bsum = runs[blockIdx.x].bsum;
+    const int nblk = (st.n_parent + kBlock - 1) / kBlock;
+    const int t = (int)threadIdx.x;
+    const int per = (nblk + 1023) / 1024;
+    const int lo = t * per, hi = min(nblk, lo + per);
+    uint32_t s = 0;
+    for (int i = lo; i < hi; ++i) s += bsum[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t y = (t >= off) ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += y;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - s;
+    for (int i = lo; i < hi; ++i) {
+        const uint32_t v = bsum[i];
+        bsum[i] = run;
+        run += v;
+    }
+    if (t == 1023) {
+        const uint32_t total = part[1023];
+        res[blockIdx.x].r_new = total;
+        res[blockIdx.x].err = total > (uint32_t)runs[blockIdx.x].capacity ? 1u : (total == 0u ? 2u : 0u);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void b_scatter(const Item* __restrict__ items, const RunDev* __restrict__ runs,
+                                                    const StepDev* __restrict__ steps,
+                                                    const ResultDev* __restrict__ res)
+{
+    const Item it = items[blockIdx.x];
+    const StepDev st = steps[it.run];
+    if (!st.active || !st.resample || it.blk * kBlock >= st.n_parent || res[it.run].err) return;
+    const RunDev& rd = runs[it.run];
+    const int j = it.blk * kBlock + (int)threadIdx.x;
+    const uint32_t c = (j < st.n_parent) ? rd.counts[j] : 0u;
+    uint32_t total;
+    const uint32_t off = rd.bsum[it.blk] + block_exclusive_scan(c, &total);
+    for (uint32_t k = 0; k < c; ++k) rd.parent[off + k] = (uint32_t)j;
+}
+
+// Item blk covers 16-byte chunks [blk * kBlock, (blk + 1) * kBlock) of the run's new population.
+__global__ __launch_bounds__(kBlock) void b_copy(const Item* __restrict__ items, const RunDev* __restrict__ runs,
+                                                 const StepDev* __restrict__ steps, const ResultDev* __restrict__ res)
+{
+    const Item it = items[blockIdx.x];
+    const StepDev st = steps[it.run];
+    if (!st.active || !st.resample || res[it.run].err) return;
+    const RunDev& rd = runs[it.run];
+    const uint32_t chunks = rd.rep_bytes / 16;
+    const size_t total = (size_t)res[it.run].r_new * chunks;
+    const size_t i = (size_t)it.blk * kBlock + threadIdx.x;
+    if (i >= total) return;
+    const uint32_t child = (uint32_t)(i / chunks), ch = (uint32_t)(i % chunks);
+    const uint32_t p = rd.parent[child];
+    const uint4* src = reinterpret_cast<const uint4*>(rd.spin[st.cur]);
+    uint4* dst = reinterpret_cast<uint4*>(rd.spin[st.cur ^ 1]);
+    dst[i] = src[(size_t)p * chunks + ch];
+    if (ch == 0) {
+        rd.E[st.cur ^ 1][child] = rd.E[st.cur][p];
+        rd.M[st.cur ^ 1][child] = rd.M[st.cur][p];
+    }
+}
+
+// Item blk covers waves [blk * wpb, (blk + 1) * wpb) of the run (wpb = blockDim.x / 64).
+template <int L, bool INT8>
+__global__ __launch_bounds__(512) void b_sweep(const Item* __restrict__ items, const RunDev* __restrict__ runs,
+                                               const StepDev* __restrict__ steps, const ResultDev* __restrict__ res)
+{
+    using Gm = Geo<L>;
+    extern __shared__ uint32_t lds_dyn[];
+    const Item it = items[blockIdx.x];
+    const StepDev st = steps[it.run];
+    if (!st.active) return;
+    int buf, n;
+    if (!post_resample(st, res[it.run], &buf, &n)) return;  // failed resampling: no sweep
+    const RunDev& rd = runs[it.run];
+    SweepArgs a;
+    a.spin = rd.spin[buf];
+    a.E = rd.E[buf];
+    a.M = rd.M[buf];
+    a.n_rep = n;
+    a.nsweeps = st.nsweeps;
+    a.g0 = st.g0;
+    a.key0 = rd.key0;
+    a.key1 = rd.key1;
+    a.t2h = st.t2h;
+    a.t2l = st.t2l;
+    a.t4h = st.t4h;
+    a.t4l = st.t4l;
+    a.init = st.init;
+    const int wpb = (int)(blockDim.x >> 6);
+    if (it.blk * wpb * Gm::REPW >= n) return;  // uniform per block
+    LaneInfo li;
+    li.lane = (int)(threadIdx.x & 63u);
+    li.gl = li.lane % Gm::G;
+    const int wave = it.blk * wpb + (int)(threadIdx.x >> 6);
+    int jj = wave * Gm::REPW + li.lane / Gm::G;
+    if constexpr (Gm::REPW == 1) jj = __builtin_amdgcn_readfirstlane(jj);
+    li.j = (uint32_t)jj;
+    li.valid = jj < n;
+    if constexpr (Gm::K == 1) {
+        if (wave * Gm::REPW >= n) return;  // uniform per wave; no barriers on this path
+        sweep_regs<L, INT8>(a, li);
+    } else {
+        sweep_lds<L, INT8>(a, li, lds_dyn + (threadIdx.x >> 6) * 2 * Gm::NW);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void b_stats_reset(const RunDev* __restrict__ runs,
+                                                        const StepDev* __restrict__ steps)
+{
+    const StepDev st = steps[blockIdx.x];
+    if (!st.active) return;
+    const RunDev& rd = runs[blockIdx.x];
+    if (threadIdx.x == 0) {
+        DevStats* s = rd.stats;
+        s->emin = 0x7FFFFFFF;
+        s->emax = (int32_t)0x80000000;
+        s->r_new = 0;
+        s->pad = 0;
+        s->sumE = s->sumE2 = s->sumAbsM = s->sumM2 = s->sumM4_lo = s->sumM4_hi = 0;
+    }
+    for (int b = (int)threadIdx.x; b < rd.nbins; b += kBlock) rd.hist[b] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void b_stats(const Item* __restrict__ items, const RunDev* __restrict__ runs,
+                                                  const StepDev* __restrict__ steps, const ResultDev* __restrict__ res)
+{
+    const Item it = items[blockIdx.x];
+    const StepDev st = steps[it.run];
+    if (!st.active) return;
+    int buf, n;
+    const bool ok = post_resample(st, res[it.run], &buf, &n);
+    if (it.blk * kBlock >= n) return;
+    const RunDev& rd = runs[it.run];
+    const int i = it.blk * kBlock + (int)threadIdx.x;
+    uint64_t sE = 0, sE2 = 0, sA = 0, sM2 = 0, m4lo = 0, m4hi = 0;
+    int32_t emin = 0x7FFFFFFF, emax = (int32_t)0x80000000;
+    if (i < n) {
+        const int64_t e = rd.E[buf][i], m = rd.M[buf][i];
+        const uint64_t am = (uint64_t)(m < 0 ? -m : m);
+        const uint64_t m2 = am * am;
+        sE = (uint64_t)e;
+        sE2 = (uint64_t)(e * e);
+        sA = am;
+        sM2 = m2;
+        m4lo = m2 * m2;
+        m4hi = __umul64hi(m2, m2);
+        emin = emax = (int32_t)e;
+        const int b = (int)((e + 2 * rd.N) >> 2);
+        if (b >= 0 && b < rd.nbins) {
+            atomicAdd(&rd.hist[b], 1u);
+            if (st.record && ok) {
+                atomicAdd((unsigned long long*)&rd.mhr.H[b], 1ull);
+                atomicAdd((unsigned long long*)&rd.mhr.SA[b], (unsigned long long)am);
+                atomicAdd((unsigned long long*)&rd.mhr.SM2[b], (unsigned long long)m2);
+                atomic_add_u128(&rd.mhr.SM4[2 * b], &rd.mhr.SM4[2 * b + 1], m4lo, m4hi);
+            }
+        }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        sE += __shfl_xor(sE, off);
+        sE2 += __shfl_xor(sE2, off);
+        sA += __shfl_xor(sA, off);
+        sM2 += __shfl_xor(sM2, off);
+        const uint64_t olo = __shfl_xor(m4lo, off), ohi = __shfl_xor(m4hi, off);
+        add_u128(m4lo, m4hi, olo, ohi);
+        emin = min(emin, __shfl_xor(emin, off));
+        emax = max(emax, __shfl_xor(emax, off));
+    }
+    if ((threadIdx.x & 63u) == 0u && it.blk * kBlock + (int)(threadIdx.x & ~63u) < n) {
+        DevStats* s = rd.stats;
+        atomicAdd((unsigned long long*)&s->sumE, (unsigned long long)sE);
+        atomicAdd((unsigned long long*)&s->sumE2, (unsigned long long)sE2);
+        atomicAdd((unsigned long long*)&s->sumAbsM, (unsigned long long)sA);
+        atomicAdd((unsigned long long*)&s->sumM2, (unsigned long long)sM2);
+        atomic_add_u128(&s->sumM4_lo, &s->sumM4_hi, m4lo, m4hi);
+        atomicMin(&s->emin, emin);
+        atomicMax(&s->emax, emax);
+    }
+}
+
+__global__ void b_fill_u32(uint32_t* p, uint32_t value, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool lattice_supported(int L) { return L == 16 || L == 32 || L == 64 || L == 128 || L == 256; }
+
+int32_t default_capacity(int32_t R) { return R + (int32_t)std::ceil(10.0 * std::sqrt((double)R)) + 64; }
+
+bool valid_params(const pa_params& p)
+{
+    if (!lattice_supported(p.L) || p.R < 1) return false;
+    if (p.layout != PA_SPIN_INT8 && p.layout != PA_SPIN_BITS) return false;
+    if (p.flags & ~(uint32_t)PA_FLAG_MHR) return false;
+    const int64_t cap = p.capacity ? p.capacity : default_capacity(p.R);
+    return cap >= p.R && cap <= ((int64_t)1 << 30);
+}
+
+bool valid_schedule(const pa_schedule& s)
+{
+    if (!(s.beta_f > 0.0) || !std::isfinite(s.beta_f) || s.theta < 0) return false;
+    switch (s.mode) {
+    case PA_STEP_FIXED: return s.dbeta > 0.0 && std::isfinite(s.dbeta);
+    case PA_STEP_ADAPTIVE: return s.alpha_star > 0.0 && s.alpha_star < 1.0;
+    case PA_STEP_LEARNED: return s.alpha_star > 0.0 && s.alpha_star < 1.0 && s.alpha_tol >= 0.0;
+    default: return false;
+    }
+}
+
+// Per-run placement inside the batch workspace.
+struct RunLayout {
+    size_t spin[2], E[2], M[2], counts, parent, bsum, mhr;
+    size_t stats_off;  // offset of the stats block inside the download area
+    size_t tbl_words;  // table capacity in u32
+    int32_t capacity, nbins, nblk;
+    size_t rep_bytes;
+};
+
+struct BatchLayout {
+    std::vector<RunLayout> runs;
+    size_t rundev, steps, results, download, tables, items, total;
+    size_t download_bytes;  // results + all stats blocks and histograms
+    size_t steps_bytes;     // step descriptors + table area
+    size_t n_items;
+};
+
+struct Group {
+    int L, layout, wpb;
+    size_t item_off, n_items;
+};
+
+bool make_batch_layout(const pa_params* runs, int nruns, BatchLayout* bl)
+{
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o = align_up(o + bytes);
+        return at;
+    };
+    bl->runs.resize((size_t)nruns);
+    size_t dl = align_up(sizeof(ResultDev) * (size_t)nruns);
+    size_t tbl = 0;
+    for (int r = 0; r < nruns; ++r) {
+        const pa_params& p = runs[r];
+        if (!valid_params(p)) return false;
+        RunLayout& rl = bl->runs[(size_t)r];
+        const int64_t N = (int64_t)p.L * p.L;
+        rl.capacity = p.capacity ? p.capacity : default_capacity(p.R);
+        rl.nbins = (int32_t)N + 1;
+        rl.nblk = (rl.capacity + kBlock - 1) / kBlock;
+        rl.rep_bytes = (p.layout == PA_SPIN_INT8) ? (size_t)N : (size_t)N / 8;
+        for (int b = 0; b < 2; ++b) {
+            rl.spin[b] = take((size_t)rl.capacity * rl.rep_bytes);
+            rl.E[b] = take((size_t)rl.capacity * 4);
+            rl.M[b] = take((size_t)rl.capacity * 4);
+        }
+        rl.counts = take((size_t)rl.capacity * 4);
+        rl.parent = take((size_t)rl.capacity * 4);
+        rl.bsum = take((size_t)rl.nblk * 4 + 4);
+        rl.mhr = (p.flags & PA_FLAG_MHR) ? take((size_t)rl.nbins * 40) : 0;
+        rl.stats_off = dl;
+        dl = align_up(dl + sizeof(DevStats) + (size_t)rl.nbins * 4);
+        rl.tbl_words = (size_t)rl.nbins * 2;
+        tbl += rl.tbl_words;
+    }
+    bl->download_bytes = dl;
+    bl->steps_bytes = align_up(sizeof(StepDev) * (size_t)nruns) + tbl * 4;
+    bl->rundev = take(sizeof(RunDev) * (size_t)nruns);
+    bl->steps = take(bl->steps_bytes);
+    bl->download = take(dl);
+    bl->results = bl->download;  // results lead the download area
+    // items: parents/statistics, copy chunks, and sweep items of every candidate shape
+    size_t n_items = 0;
+    for (int r = 0; r < nruns; ++r) {
+        const RunLayout& rl = bl->runs[(size_t)r];
+        const int64_t L = runs[r].L;
+        const int64_t N = L * L, NW = N / 64, G = NW < 64 ? NW : 64, repw = 64 / G;
+        const size_t chunks = rl.rep_bytes / 16;
+        n_items += (size_t)rl.nblk;                                             // counts / scatter / stats
+        n_items += ((size_t)rl.capacity * chunks + kBlock - 1) / kBlock;          // copy
+        n_items += 2 * (size_t)((rl.capacity + repw - 1) / repw);                 // sweep, any shape (upper bound)
+    }
+    bl->n_items = n_items;
+    bl->items = take(n_items * sizeof(Item));
+    bl->tables = bl->steps + align_up(sizeof(StepDev) * (size_t)nruns);
+    bl->total = o;
+    return true;
+}
+
+// Minimal fork-join pool for the per-run host work.
+class Pool {
+public:
+    explicit Pool(int n) : nthreads_(std::max(1, n)) {
+        for (int i = 1; i < nthreads_; ++i) workers_.emplace_back([this, i] { loop(i); });
+    }
+    ~Pool() {
+        {
+            std::lock_guard<std::mutex> g(m_);
+            stop_ = true;
+            ++gen_;
+        }
+        cv_.notify_all();
+        for (auto& t : workers_) t.join();
+    }
+    void parallel_for(int n, const std::function<void(int)>& fn) {
+        if (nthreads_ == 1 || n <= 1) {
+            for (int i = 0; i < n; ++i) fn(i);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> g(m_);
+            fn_ = &fn;
+            n_ = n;
+            next_.store(0);
+            pending_ = nthreads_ - 1;
+            ++gen_;
+        }
+        cv_.notify_all();
+        run_items();
+        std::unique_lock<std::mutex> lk(m_);
+        done_cv_.wait(lk, [this] { return pending_ == 0; });
+        fn_ = nullptr;
+    }
+
+private:
+    void run_items() {
+        for (;;) {
+            const int i = next_.fetch_add(1);
+            if (i >= n_) break;
+            (*fn_)(i);
+        }
+    }
+    void loop(int) {
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(m_);
+                cv_.wait(lk, [&] { return gen_ != seen; });
+                seen = gen_;
+                if (stop_) return;
+            }
+            run_items();
+            {
+                std::lock_guard<std::mutex> g(m_);
+                if (--pending_ == 0) done_cv_.notify_one();
+            }
+        }
+    }
+    int nthreads_;
+    std::vector<std::thread> workers_;
+    std::mutex m_;
+    std::condition_variable cv_, done_cv_;
+    const std::function<void(int)>* fn_ = nullptr;
+    int n_ = 0;
+    std::atomic<int> next_{0};
+    int pending_ = 0;
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
+
+}  // namespace batch
+}  // namespace pa
+
+using namespace pa::batch;
+using pa::DevMhr;
+using pa::DevStats;
+using pa::kBlock;
+namespace host = pa::host;
+
+struct RunHost {
+    pa_params p;
+    pa_schedule sched;
+    int64_t R_cur = 0;
+    int32_t step = 0;
+    uint64_t sweeps = 0;
+    double beta = 0.0, lnZ = 0.0, lnQ_last = 0.0;
+    int cur = 0;
+    pa_status status = PA_OK;
+    bool finished = false;
+    // pending step
+    bool stepping = false;
+    double beta_next = 0.0, lnQ_next = 0.0;
+    std::vector<pa_obs> history;
+    std::vector<double> m_beta, m_lnZ;
+    std::vector<int64_t> m_R;
+    std::vector<double> w;  // scratch
+    DevStats h_stats;
+    const uint32_t* h_hist = nullptr;
+};
+
+struct pa_batch {
+    int nruns = 0;
+    BatchLayout lo;
+    uint8_t* ws = nullptr;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::vector<RunHost> runs;
+    std::vector<RunDev> rundev;
+    RunDev* d_rundev = nullptr;
+    StepDev* d_steps = nullptr;
+    uint32_t* d_tables = nullptr;
+    ResultDev* d_results = nullptr;
+    uint8_t* d_download = nullptr;
+    Item* d_items = nullptr;
+    // items: parents, copy, and sweep items per group
+    size_t parent_off = 0, n_parent_items = 0, copy_off = 0, n_copy_items = 0;
+    std::vector<Group> groups;
+    uint8_t* h_steps = nullptr;     // pinned: step descriptors + tables
+    uint8_t* h_download = nullptr;  // pinned: results + statistics
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    pa::batch::Pool* pool = nullptr;
+    bool broken = false;
+    std::string last_error;
+};
+
+namespace {
+
+pa_status fail_hip(pa_batch* b, hipError_t e, const char* what)
+{
+    b->broken = true;
+    b->last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return PA_EHIP;
+}
+
+#define BCHK(expr)                                            \
+    do {                                                      \
+        const hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) return fail_hip(b, e_, #expr);  \
+    } while (0)
+
+template <int L, bool INT8>
+hipError_t launch_group_t(const Item* items, size_t n, int wpb, const RunDev* rd, const StepDev* st,
+                          const ResultDev* rs, hipStream_t s)
+{
+    using Gm = pa::dev::Geo<L>;
+    const size_t lds = (Gm::K == 1) ? 0 : (size_t)wpb * 2 * Gm::NW * 4;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL((b_sweep<L, INT8>), dim3((unsigned)n), dim3(64 * wpb), lds, s, items, rd, st, rs);
+    return hipGetLastError();
+}
+
+hipError_t launch_group(int L, int layout, const Item* items, size_t n, int wpb, const RunDev* rd, const StepDev* st,
+                        const ResultDev* rs, hipStream_t s)
+{
+    const bool i8 = layout == PA_SPIN_INT8;
+    switch (L) {
+    case 16: return i8 ? launch_group_t<16, true>(items, n, wpb, rd, st, rs, s) : launch_group_t<16, false>(items, n, wpb, rd, st, rs, s);
+    case 32: return i8 ? launch_group_t<32, true>(items, n, wpb, rd, st, rs, s) : launch_group_t<32, false>(items, n, wpb, rd, st, rs, s);
+    case 64: return i8 ? launch_group_t<64, true>(items, n, wpb, rd, st, rs, s) : launch_group_t<64, false>(items, n, wpb, rd, st, rs, s);
+    case 128: return i8 ? launch_group_t<128, true>(items, n, wpb, rd, st, rs, s) : launch_group_t<128, false>(items, n, wpb, rd, st, rs, s);
+    case 256: return i8 ? launch_group_t<256, true>(items, n, wpb, rd, st, rs, s) : launch_group_t<256, false>(items, n, wpb, rd, st, rs, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int reps_per_wave(int L)
+{
+    const int NW = L * L / 64;
+    const int G = NW < 64 ? NW : 64;
+    return 64 / G;
+}
+
+// Sweep items of one group for a given number of waves per block.
+std::vector<Item> sweep_items(const pa_batch* b, int L, int layout, int wpb)
+{
+    std::vector<Item> it;
+    const int per_block = reps_per_wave(L) * wpb;
+    for (int r = 0; r < b->nruns; ++r) {
+        const pa_params& p = b->runs[(size_t)r].p;
+        if (p.L != L || p.layout != layout) continue;
+        const int cap = b->lo.runs[(size_t)r].capacity;
+        const int nb = (cap + per_block - 1) / per_block;
+        for (int k = 0; k < nb; ++k) it.push_back(Item{r, k});
+    }
+    return it;
+}
+
+// Enqueue the device part of one step (captured into the graph).
+pa_status enqueue_step(pa_batch* b)
+{
+    const hipStream_t s = b->stream;
+    const Item* items = b->d_items;
+    if (b->n_parent_items) {
+        hipLaunchKernelGGL(b_counts, dim3((unsigned)b->n_parent_items), dim3(kBlock), 0, s, items + b->parent_off,
+                           b->d_rundev, b->d_steps, b->d_tables);
+        BCHK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(b_scan, dim3((unsigned)b->nruns), dim3(1024), 0, s, b->d_rundev, b->d_steps, b->d_results);
+    BCHK(hipGetLastError());
+    hipLaunchKernelGGL(b_scatter, dim3((unsigned)b->n_parent_items), dim3(kBlock), 0, s, items + b->parent_off,
+                       b->d_rundev, b->d_steps, b->d_results);
+    BCHK(hipGetLastError());
+    if (b->n_copy_items) {
+        hipLaunchKernelGGL(b_copy, dim3((unsigned)b->n_copy_items), dim3(kBlock), 0, s, items + b->copy_off,
+                           b->d_rundev, b->d_steps, b->d_results);
+        BCHK(hipGetLastError());
+    }
+    for (const Group& g : b->groups)
+        BCHK(launch_group(g.L, g.layout, items + g.item_off, g.n_items, g.wpb, b->d_rundev, b->d_steps,
+                          b->d_results, s));
+    hipLaunchKernelGGL(b_stats_reset, dim3((unsigned)b->nruns), dim3(kBlock), 0, s, b->d_rundev, b->d_steps);
+    BCHK(hipGetLastError());
+    hipLaunchKernelGGL(b_stats, dim3((unsigned)b->n_parent_items), dim3(kBlock), 0, s, items + b->parent_off,
+                       b->d_rundev, b->d_steps, b->d_results);
+    BCHK(hipGetLastError());
+    BCHK(hipMemcpyAsync(b->h_download, b->d_download, b->lo.download_bytes, hipMemcpyDeviceToHost, s));
+    return PA_OK;
+}
+
+StepDev* host_steps(pa_batch* b) { return reinterpret_cast<StepDev*>(b->h_steps); }
+uint32_t* host_tables(pa_batch* b)
+{
+    return reinterpret_cast<uint32_t*>(b->h_steps + (b->lo.tables - b->lo.steps));
+}
+
+// Runs one replay of the step graph after uploading the first `bytes` bytes
+// of the step descriptors and packed tables.
+pa_status replay(pa_batch* b, size_t bytes)
+{
+    BCHK(hipMemcpyAsync(b->d_steps, b->h_steps, bytes, hipMemcpyHostToDevice, b->stream));
+    BCHK(hipGraphLaunch(b->exec, b->stream));
+    BCHK(hipStreamSynchronize(b->stream));
+    return PA_OK;
+}
+
+void read_stats(pa_batch* b, int r)
+{
+    RunHost& h = b->runs[(size_t)r];
+    const RunLayout& rl = b->lo.runs[(size_t)r];
+    std::memcpy(&h.h_stats, b->h_download + rl.stats_off, sizeof(DevStats));
+    h.h_hist = reinterpret_cast<const uint32_t*>(b->h_download + rl.stats_off + sizeof(DevStats));
+}
+
+void record_measurement(RunHost& h)
+{
+    pa_obs o;
+    host::observables(h.h_stats, h.R_cur, h.p.L * h.p.L, h.beta, h.lnZ, h.lnQ_last, &o);
+    h.history.push_back(o);
+    if (h.p.flags & PA_FLAG_MHR) {
+        h.m_beta.push_back(h.beta);
+        h.m_lnZ.push_back(h.lnZ);
+        h.m_R.push_back(h.R_cur);
+    }
+}
+
+// Next inverse temperature of a run, or false (with the run's status set).
+bool choose_beta(RunHost& h, const host::Hist& hw, double* beta_next)
+{
+    const pa_schedule& s = h.sched;
+    if (s.mode == PA_STEP_FIXED) {
+        const int64_t nb = std::max<int64_t>(1, std::llround(s.beta_f / s.dbeta));
+        const int64_t i = (int64_t)h.step + 1;
+        *beta_next = (i >= nb) ? s.beta_f : (double)i * s.dbeta;
+        if (*beta_next > s.beta_f) *beta_next = s.beta_f;
+        return true;
+    }
+    double a = 0.0;
+    if (!host::adapt_beta(hw, h.p.R, h.R_cur, h.beta, s.beta_f, s.alpha_star, beta_next, &a, h.w)) {
+        h.status = PA_EINVAL;
+        return false;
+    }
+    return true;
+}
+
+pa_status autotune(pa_batch* b);
+
+}  // namespace
+
+extern "C" {
+
+size_t pa_batch_workspace_bytes(const pa_params* runs, int32_t nruns)
+{
+    if (!runs || nruns < 1) return 0;
+    BatchLayout bl;
+    return make_batch_layout(runs, nruns, &bl) ? bl.total : 0;
+}
+
+static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int32_t nruns, void* d_workspace,
+                            size_t bytes, void* hip_stream, pa_batch** out);
+
+pa_status pa_batch_init(const pa_params* runs, const pa_schedule* sched, int32_t nruns, void* d_workspace,
+                        size_t bytes, void* hip_stream, pa_batch** out)
+{
+    if (!out) return PA_EINVAL;
+    *out = nullptr;
+    pa_batch* b = nullptr;
+    const pa_status st = batch_init(runs, sched, nruns, d_workspace, bytes, hip_stream, &b);
+    if (st != PA_OK) {
+        if (b && b->stream) (void)hipStreamSynchronize(b->stream);
+        pa_batch_free(b);
+        return st;
+    }
+    *out = b;
+    return PA_OK;
+}
+
+static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int32_t nruns, void* d_workspace,
+                            size_t bytes, void* hip_stream, pa_batch** out)
+{
+    if (!runs || !sched || nruns < 1 || !d_workspace || ((uintptr_t)d_workspace) % kAlign) return PA_EINVAL;
+    for (int r = 0; r < nruns; ++r)
+        if (!valid_schedule(sched[r])) return PA_EINVAL;
+    BatchLayout bl;
+    if (!make_batch_layout(runs, nruns, &bl)) return PA_EINVAL;
+    if (bytes < bl.total) return PA_ENOMEM;
+    pa_batch* b = new (std::nothrow) pa_batch();
+    if (!b) return PA_ENOMEM;
+    b->nruns = nruns;
+    b->lo = bl;
+    b->ws = (uint8_t*)d_workspace;
+    *out = b;
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        BCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+        b->own_stream = true;
+    }
+    uint8_t* ws = b->ws;
+    b->d_rundev = reinterpret_cast<RunDev*>(ws + bl.rundev);
+    b->d_steps = reinterpret_cast<StepDev*>(ws + bl.steps);
+    b->d_tables = reinterpret_cast<uint32_t*>(ws + bl.tables);
+    b->d_download = ws + bl.download;
+    b->d_results = reinterpret_cast<ResultDev*>(ws + bl.results);
+    b->d_items = reinterpret_cast<Item*>(ws + bl.items);
+    b->runs.resize((size_t)nruns);
+    b->rundev.resize((size_t)nruns);
+    for (int r = 0; r < nruns; ++r) {
+        const RunLayout& rl = bl.runs[(size_t)r];
+        RunHost& h = b->runs[(size_t)r];
+        h.p = runs[r];
+        h.p.capacity = rl.capacity;
+        h.sched = sched[r];
+        RunDev& d = b->rundev[(size_t)r];
+        std::memset(&d, 0, sizeof(d));
+        for (int k = 0; k < 2; ++k) {
+            d.spin[k] = ws + rl.spin[k];
+            d.E[k] = reinterpret_cast<int32_t*>(ws + rl.E[k]);
+            d.M[k] = reinterpret_cast<int32_t*>(ws + rl.M[k]);
+        }
+        d.counts = reinterpret_cast<uint32_t*>(ws + rl.counts);
+        d.parent = reinterpret_cast<uint32_t*>(ws + rl.parent);
+        d.bsum = reinterpret_cast<uint32_t*>(ws + rl.bsum);
+        d.stats = reinterpret_cast<DevStats*>(b->d_download + rl.stats_off);
+        d.hist = reinterpret_cast<uint32_t*>(b->d_download + rl.stats_off + sizeof(DevStats));
+        if (h.p.flags & PA_FLAG_MHR) {
+            uint64_t* m = reinterpret_cast<uint64_t*>(ws + rl.mhr);
+            d.mhr = DevMhr{m, m + rl.nbins, m + 2 * (size_t)rl.nbins, m + 3 * (size_t)rl.nbins};
+        }
+        d.L = h.p.L;
+        d.N = h.p.L * h.p.L;
+        d.nbins = rl.nbins;
+        d.capacity = rl.capacity;
+        d.layout = h.p.layout;
+        d.R = h.p.R;
+        d.rep_bytes = (uint32_t)rl.rep_bytes;
+        d.key0 = (uint32_t)h.p.seed;
+        d.key1 = (uint32_t)(h.p.seed >> 32) ^ h.p.run_id;
+    }
+    if (hipHostMalloc((void**)&b->h_steps, bl.steps_bytes, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->h_download, bl.download_bytes, hipHostMallocDefault) != hipSuccess)
+        return PA_ENOMEM;
+    std::memset(b->h_steps, 0, bl.steps_bytes);
+    BCHK(hipMemcpyAsync(b->d_rundev, b->rundev.data(), sizeof(RunDev) * (size_t)nruns, hipMemcpyHostToDevice,
+                        b->stream));
+    for (int r = 0; r < nruns; ++r) {
+        const RunDev& d = b->rundev[(size_t)r];
+        if (d.mhr.H) {
+            hipLaunchKernelGGL(b_fill_u32, dim3(256), dim3(kBlock), 0, b->stream, (uint32_t*)d.mhr.H, 0u,
+                               (size_t)d.nbins * 10);
+            BCHK(hipGetLastError());
+        }
+    }
+    // static item tables: parents/statistics and copy chunks
+    std::vector<Item> items;
+    b->parent_off = 0;
+    for (int r = 0; r < nruns; ++r)
+        for (int k = 0; k < bl.runs[(size_t)r].nblk; ++k) items.push_back(Item{r, k});
+    b->n_parent_items = items.size();
+    b->copy_off = items.size();
+    for (int r = 0; r < nruns; ++r) {
+        const RunLayout& rl = bl.runs[(size_t)r];
+        const size_t n = ((size_t)rl.capacity * (rl.rep_bytes / 16) + kBlock - 1) / kBlock;
+        for (size_t k = 0; k < n; ++k) items.push_back(Item{r, (int32_t)k});
+    }
+    b->n_copy_items = items.size() - b->copy_off;
+    // sweep groups, one per (L, store)
+    std::map<std::pair<int, int>, int> seen;
+    for (int r = 0; r < nruns; ++r) {
+        const auto key = std::make_pair(runs[r].L, runs[r].layout);
+        if (!seen.count(key)) {
+            seen[key] = (int)b->groups.size();
+            b->groups.push_back(Group{runs[r].L, runs[r].layout, 1, 0, 0});
+        }
+    }
+    b->pool = new (std::nothrow) Pool((int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency())));
+    if (!b->pool) return PA_ENOMEM;
+    // launch shapes, then the sweep items of the chosen shapes
+    const size_t fixed_items = items.size();
+    for (Group& g : b->groups) {
+        g.item_off = items.size();
+        const std::vector<Item> it = sweep_items(b, g.L, g.layout, 1);
+        items.insert(items.end(), it.begin(), it.end());
+        g.n_items = it.size();
+    }
+    if (items.size() > bl.n_items) return PA_ENOMEM;
+    BCHK(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, b->stream));
+    BCHK(hipStreamSynchronize(b->stream));
+    pa_status st = autotune(b);
+    if (st != PA_OK) return st;
+    items.resize(fixed_items);
+    for (Group& g : b->groups) {
+        g.item_off = items.size();
+        const std::vector<Item> it = sweep_items(b, g.L, g.layout, g.wpb);
+        items.insert(items.end(), it.begin(), it.end());
+        g.n_items = it.size();
+    }
+    BCHK(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, b->stream));
+    // capture one step
+    BCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    st = enqueue_step(b);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(b->stream, &g);
+    if (st != PA_OK) return st;
+    BCHK(ce);
+    b->graph = g;
+    BCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    // initial state (Sec. 2.1 step 1) and the measurement at beta_0 = 0
+    StepDev* sd = host_steps(b);
+    for (int r = 0; r < nruns; ++r) {
+        RunHost& h = b->runs[(size_t)r];
+        StepDev& d = sd[r];
+        std::memset(&d, 0, sizeof(d));
+        d.active = 1;
+        d.init = 1;
+        d.record = (h.p.flags & PA_FLAG_MHR) ? 1 : 0;
+        d.n_parent = h.p.R;
+        host::thresholds(0.0, &d.t2h, &d.t2l, &d.t4h, &d.t4l);
+        h.R_cur = h.p.R;
+        h.lnZ = (double)(h.p.L * h.p.L) * std::log(2.0);
+    }
+    st = replay(b, b->lo.tables - b->lo.steps);
+    if (st != PA_OK) return st;
+    for (int r = 0; r < nruns; ++r) {
+        read_stats(b, r);
+        record_measurement(b->runs[(size_t)r]);
+    }
+    return PA_OK;
+}
+
+pa_status pa_batch_step(pa_batch* b, int32_t* n_active)
+{
+    if (!b) return PA_EINVAL;
+    if (b->broken) return PA_ESTATE;
+    StepDev* sd = host_steps(b);
+    uint32_t* tb = host_tables(b);
+    // phase 1 (per run): next beta
+    b->pool->parallel_for(b->nruns, [&](int r) {
+        RunHost& h = b->runs[(size_t)r];
+        h.stepping = false;
+        if (h.finished || h.status != PA_OK) return;
+        const host::Hist hw = host::hist_window(h.h_hist, h.h_stats, h.p.L * h.p.L);
+        double bn = 0.0;
+        if (!choose_beta(h, hw, &bn)) return;
+        h.beta_next = bn;
+        h.stepping = true;
+    });
+    // phase 2: pack the table windows
+    std::vector<uint32_t> toff((size_t)b->nruns, 0u);
+    uint32_t o = 0;
+    int any = 0;
+    for (int r = 0; r < b->nruns; ++r) {
+        const RunHost& h = b->runs[(size_t)r];
+        if (!h.stepping) continue;
+        ++any;
+        toff[(size_t)r] = o;
+        const int bmin = (h.h_stats.emin + 2 * h.p.L * h.p.L) / 4, bmax = (h.h_stats.emax + 2 * h.p.L * h.p.L) / 4;
+        o += 2u * (uint32_t)(bmax - bmin + 1);
+    }
+    // phase 3 (per run): tables of Eq. (resampling factors) and the step descriptor
+    b->pool->parallel_for(b->nruns, [&](int r) {
+        RunHost& h = b->runs[(size_t)r];
+        StepDev& d = sd[r];
+        std::memset(&d, 0, sizeof(d));
+        if (!h.stepping) return;
+        const host::Hist hw = host::hist_window(h.h_hist, h.h_stats, h.p.L * h.p.L);
+        const double bn = h.beta_next;
+        h.lnQ_next = host::resample_tables(hw, h.p.R, h.R_cur, bn - h.beta, tb + toff[(size_t)r], h.w);
+        d.active = 1;
+        d.resample = 1;
+        d.record = (h.p.flags & PA_FLAG_MHR) ? 1 : 0;
+        d.cur = h.cur;
+        d.n_parent = (int32_t)h.R_cur;
+        d.step = (uint32_t)(h.step + 1);
+        d.g0 = (uint32_t)h.sweeps;
+        d.nsweeps = h.sched.theta;
+        host::thresholds(bn, &d.t2h, &d.t2l, &d.t4h, &d.t4l);
+        d.bmin = hw.bmin;
+        d.nwin = hw.bmax - hw.bmin + 1;
+        d.tbl_off = toff[(size_t)r];
+    });
+    if (any) {
+        const pa_status st = replay(b, (b->lo.tables - b->lo.steps) + (size_t)o * 4);
+        if (st != PA_OK) return st;
+        const ResultDev* res = reinterpret_cast<const ResultDev*>(b->h_download);
+        b->pool->parallel_for(b->nruns, [&](int r) {
+            RunHost& h = b->runs[(size_t)r];
+            if (!h.stepping) return;
+            h.stepping = false;
+            if (res[r].err) {
+                h.status = (res[r].err == 1) ? PA_ECAPACITY : PA_EEXTINCT;
+                read_stats(b, r);  // statistics of the unchanged population
+                return;
+            }
+            h.cur ^= 1;
+            h.R_cur = res[r].r_new;
+            h.step += 1;
+            h.sweeps += (uint64_t)h.sched.theta;
+            h.beta = h.beta_next;
+            h.lnZ += h.lnQ_next;
+            h.lnQ_last = h.lnQ_next;
+            read_stats(b, r);
+            record_measurement(h);
+            if (h.beta >= h.sched.beta_f) h.finished = true;
+        });
+    }
+    if (n_active) {
+        int n = 0;
+        for (const RunHost& h : b->runs) n += (!h.finished && h.status == PA_OK) ? 1 : 0;
+        *n_active = n;
+    }
+    return PA_OK;
+}
+
+pa_status pa_batch_run(pa_batch* b)
+{
+    if (!b) return PA_EINVAL;
+    int32_t n = 1;
+    while (n > 0) {
+        const pa_status st = pa_batch_step(b, &n);
+        if (st != PA_OK) return st;
+    }
+    return PA_OK;
+}
+
+pa_status pa_batch_run_status(const pa_batch* b, int32_t run)
+{
+    if (!b || run < 0 || run >= b->nruns) return PA_EINVAL;
+    return b->runs[(size_t)run].status;
+}
+
+pa_status pa_batch_state(const pa_batch* b, int32_t run, pa_state_info* out)
+{
+    if (!b || !out || run < 0 || run >= b->nruns) return PA_EINVAL;
+    const RunHost& h = b->runs[(size_t)run];
+    out->R = h.R_cur;
+    out->step = h.step;
+    out->sweeps = h.sweeps;
+    out->beta = h.beta;
+    out->lnZ = h.lnZ;
+    return PA_OK;
+}
+
+pa_status pa_batch_history(const pa_batch* b, int32_t run, pa_obs* out, int32_t cap, int32_t* n)
+{
+    if (!b || !n || run < 0 || run >= b->nruns || cap < 0 || (cap > 0 && !out)) return PA_EINVAL;
+    const RunHost& h = b->runs[(size_t)run];
+    *n = (int32_t)h.history.size();
+    const size_t k = std::min<size_t>((size_t)cap, h.history.size());
+    if (k) std::memcpy(out, h.history.data(), k * sizeof(pa_obs));
+    return PA_OK;
+}
+
+pa_status pa_batch_reweight(pa_batch* b, int32_t run, const double* betas, int32_t nb, pa_obs* out)
+{
+    if (!b || run < 0 || run >= b->nruns || nb < 0 || (nb > 0 && (!betas || !out))) return PA_EINVAL;
+    if (b->broken) return PA_ESTATE;
+    const RunHost& h = b->runs[(size_t)run];
+    const RunDev& d = b->rundev[(size_t)run];
+    if (!(h.p.flags & PA_FLAG_MHR) || h.m_beta.empty()) return PA_EINVAL;
+    const size_t nbins = (size_t)d.nbins;
+    std::vector<uint64_t> acc(5 * nbins);
+    BCHK(hipMemcpyAsync(acc.data(), d.mhr.H, acc.size() * 8, hipMemcpyDeviceToHost, b->stream));
+    BCHK(hipStreamSynchronize(b->stream));
+    const uint64_t* H = acc.data();
+    host::reweight(d.N, H, H + nbins, H + 2 * nbins, H + 3 * nbins, h.m_beta, h.m_lnZ, h.m_R, betas, nb, out);
+    return PA_OK;
+}
+
+pa_status pa_batch_download_population(pa_batch* b, int32_t run, int8_t* spins, int32_t* E, int32_t* M)
+{
+    if (!b || run < 0 || run >= b->nruns) return PA_EINVAL;
+    if (b->broken) return PA_ESTATE;
+    const RunHost& h = b->runs[(size_t)run];
+    const RunDev& d = b->rundev[(size_t)run];
+    const size_t n = (size_t)h.R_cur;
+    if (E) BCHK(hipMemcpyAsync(E, d.E[h.cur], n * 4, hipMemcpyDeviceToHost, b->stream));
+    if (M) BCHK(hipMemcpyAsync(M, d.M[h.cur], n * 4, hipMemcpyDeviceToHost, b->stream));
+    if (spins) {
+        if (h.p.layout == PA_SPIN_INT8) {
+            BCHK(hipMemcpyAsync(spins, d.spin[h.cur], n * (size_t)d.N, hipMemcpyDeviceToHost, b->stream));
+        } else {
+            std::vector<uint32_t> words(n * (size_t)d.N / 32);
+            BCHK(hipMemcpyAsync(words.data(), d.spin[h.cur], words.size() * 4, hipMemcpyDeviceToHost, b->stream));
+            BCHK(hipStreamSynchronize(b->stream));
+            host::bits_to_int8(words.data(), d.L, n, spins);
+        }
+    }
+    BCHK(hipStreamSynchronize(b->stream));
+    return PA_OK;
+}
+
+pa_status pa_batch_free(pa_batch* b)
+{
+    if (!b) return PA_OK;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->h_steps) (void)hipHostFree(b->h_steps);
+    if (b->h_download) (void)hipHostFree(b->h_download);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b->pool;
+    delete b;
+    return PA_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Picks waves per block for every (L, store) group by timing the sweep on the
+// spare half of each run's ping-pong store: the spare buffers are overwritten
+// by the first resampling, so tuning leaves no trace in the runs.  The timed
+// launches draw a fresh state and do a few sweeps at beta = 0.44.
+pa_status autotune(pa_batch* b)
+{
+    const int cands[] = {1, 2, 4, 8};
+    StepDev* sd = host_steps(b);
+    hipEvent_t e0, e1;
+    BCHK(hipEventCreate(&e0));
+    BCHK(hipEventCreate(&e1));
+    std::vector<Item> it;
+    for (Group& g : b->groups) {
+        for (int r = 0; r < b->nruns; ++r) {
+            StepDev& d = sd[r];
+            std::memset(&d, 0, sizeof(d));
+            const RunHost& h = b->runs[(size_t)r];
+            if (h.p.L != g.L || h.p.layout != g.layout) continue;
+            d.active = 1;
+            d.init = 1;
+            d.cur = 1;  // spare buffer
+            d.n_parent = h.p.R;
+            d.nsweeps = 4;
+            d.g0 = 0x40000000u;
+            host::thresholds(0.44, &d.t2h, &d.t2l, &d.t4h, &d.t4l);
+        }
+        BCHK(hipMemcpyAsync(b->d_steps, b->h_steps, b->lo.steps_bytes, hipMemcpyHostToDevice, b->stream));
+        float best = 1e30f;
+        int best_w = 1;
+        for (int wpb : cands) {
+            if (g.L >= 128 && wpb > 4) continue;  // LDS path: at most 4 replicas (32 KB) per block
+            it = sweep_items(b, g.L, g.layout, wpb);
+            const size_t off = g.item_off;  // scratch slot: the group's own item range is large enough
+            BCHK(hipMemcpyAsync(b->d_items + off, it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice,
+                                b->stream));
+            float t = 0.0f;
+            for (int rep = 0; rep < 3; ++rep) {
+                BCHK(hipEventRecord(e0, b->stream));
+                BCHK(launch_group(g.L, g.layout, b->d_items + off, it.size(), wpb, b->d_rundev, b->d_steps,
+                                  b->d_results, b->stream));
+                BCHK(hipEventRecord(e1, b->stream));
+                BCHK(hipEventSynchronize(e1));
+                float ms = 0.0f;
+                BCHK(hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0) t += ms;  // the first launch warms up
+            }
+            if (t < best) {
+                best = t;
+                best_w = wpb;
+            }
+        }
+        g.wpb = best_w;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::memset(sd, 0, sizeof(StepDev) * (size_t)b->nruns);
+    return PA_OK;
+}
+
+}  // namespace

@@ -17,488 +17,12 @@
 // compared to the integer threshold one bit plane at a time (16 planes from
 // four Philox blocks, high bit first), and the planes stop as soon as no site
 // in the wave is still undecided.
-#include "pa_internal.h"
+#include "pa_device.h"
 
 namespace pa {
 namespace {
 
-constexpr uint32_t kM0 = 0xD2511F53u;
-constexpr uint32_t kM1 = 0xCD9E8D57u;
-constexpr uint32_t kW0 = 0x9E3779B9u;
-constexpr uint32_t kW1 = 0xBB67AE85u;
-
-struct U4 {
-    uint32_t x, y, z, w;
-};
-
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32->64
-// multiplies, xor of the high halves with the other words and the round key.
-// The three-way xors are single v_bitop3 instructions (truth table 0x96).
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
-{
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
-}
-
-__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                                       uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)kM0 * c0;
-        const uint64_t p1 = (uint64_t)kM1 * c2;
-        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
-        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
-        c0 = n0;
-        c2 = n2;
-        k0 += kW0;
-        k1 += kW1;
-    }
-    return {c0, c1, c2, c3};
-}
-
-__device__ __forceinline__ uint32_t pick(const U4& v, uint32_t i)
-{
-    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
-}
-
-// Random-stream tags (counter word 3).
-constexpr uint32_t kStreamSweepHigh = 0;
-constexpr uint32_t kStreamResample = 1;
-constexpr uint32_t kStreamInit = 2;
-constexpr uint32_t kStreamSweepLow = 3;
-
-template <int L>
-struct Geo {
-    static constexpr int N = L * L;
-    static constexpr int HW = L / 2;                  // sites per row of one colour
-    static constexpr int NW = N / 64;                 // 32-site words per colour
-    static constexpr int G = NW < 64 ? NW : 64;       // lanes sharing one replica
-    static constexpr int K = NW / G;                  // words per lane per colour
-    static constexpr int REPW = 64 / G;               // replicas per wave
-    static constexpr bool WIDE = HW >= 32;            // rows made of whole words
-    static constexpr int WPR = WIDE ? HW / 32 : 1;    // words per row (wide)
-    static constexpr int RL = WIDE ? K / WPR : 1;     // rows per lane (wide)
-    static constexpr int RPW = WIDE ? 1 : 32 / HW;    // rows per word (narrow)
-    static constexpr size_t BITS_BYTES = N / 8;       // bytes per replica, bit store
-    static_assert(L % 16 == 0 && L >= 16 && L <= 256, "lattice size");
-    static_assert(K >= 1 && NW % G == 0, "lane mapping");
-};
-
-// Segment masks for narrow rows (HW < 32): bit 0 / top bit of every row
-// segment, and the segments of even rows inside a word.
-template <int HW>
-struct Seg {
-    static constexpr uint32_t seg = (HW >= 32) ? 0xFFFFFFFFu : ((1u << (HW % 32)) - 1u);
-    static constexpr uint32_t low()
-    {
-        uint32_t m = 0;
-        for (int o = 0; o < 32; o += HW) m |= 1u << o;
-        return m;
-    }
-    static constexpr uint32_t high() { return low() << (HW - 1); }
-    static constexpr uint32_t even()
-    {
-        uint32_t m = 0;
-        for (int o = 0; o < 32; o += 2 * HW) m |= seg << o;
-        return m;
-    }
-};
-
-// Value held by the lane `delta` positions away inside the same G-lane group.
-template <int G>
-__device__ __forceinline__ uint32_t from_lane(uint32_t v, int lane, int delta)
-{
-    const int base = lane & ~(G - 1);
-    const int src = base + ((lane - base + delta + G) & (G - 1));
-    return (uint32_t)__shfl((int)v, src);
-}
-
-// Neighbour words (other colour) of one own word of colour C.
-struct Nb {
-    uint32_t up, dn, same, side;
-};
-
-template <int L, int C>
-struct Neighbours {
-    using Gm = Geo<L>;
-    // boundary words fetched from the adjacent lanes, one set per half sweep
-    uint32_t upb[Gm::WPR], dnb[Gm::WPR];
-    int lane, gl;
-
-    __device__ __forceinline__ Neighbours(const uint32_t (&oth)[Gm::K], int lane_, int gl_) : lane(lane_), gl(gl_)
-    {
-        if constexpr (Gm::WIDE) {
-#pragma unroll
-            for (int t = 0; t < Gm::WPR; ++t) {
-                upb[t] = from_lane<Gm::G>(oth[(Gm::RL - 1) * Gm::WPR + t], lane, -1);
-                dnb[t] = from_lane<Gm::G>(oth[t], lane, +1);
-            }
-        } else {
-            upb[0] = from_lane<Gm::G>(oth[0], lane, -1);
-            dnb[0] = from_lane<Gm::G>(oth[0], lane, +1);
-        }
-    }
-
-    __device__ __forceinline__ Nb get(const uint32_t (&oth)[Gm::K], int k) const
-    {
-        Nb n;
-        if constexpr (Gm::WIDE) {
-            const int r = k / Gm::WPR, t = k % Gm::WPR;
-            const int tp = (t + Gm::WPR - 1) % Gm::WPR, tn = (t + 1) % Gm::WPR;
-            const uint32_t cur = oth[k];
-            n.same = cur;
-            n.up = (r > 0) ? oth[k - Gm::WPR] : upb[t];
-            n.dn = (r < Gm::RL - 1) ? oth[k + Gm::WPR] : dnb[t];
-            // (y + C) even: horizontal neighbour at h-1, else at h+1
-            const uint32_t hm1 = __builtin_amdgcn_alignbit(cur, oth[r * Gm::WPR + tp], 31);
-            const uint32_t hp1 = __builtin_amdgcn_alignbit(oth[r * Gm::WPR + tn], cur, 1);
-            if constexpr (Gm::RL % 2 == 0) {
-                n.side = (((r + C) & 1) == 0) ? hm1 : hp1;
-            } else {
-                const int y = gl * Gm::RL + r;
-                n.side = (((y + C) & 1) == 0) ? hm1 : hp1;
-            }
-        } else {
-            constexpr int HW = Gm::HW;
-            using S = Seg<HW>;
-            const uint32_t o = oth[0];
-            n.same = o;
-            n.up = __builtin_amdgcn_alignbit(o, upb[0], 32 - HW);
-            n.dn = __builtin_amdgcn_alignbit(dnb[0], o, HW);
-            const uint32_t rotl = ((o << 1) & ~S::low()) | ((o >> (HW - 1)) & S::low());
-            const uint32_t rotr = ((o >> 1) & ~S::high()) | ((o << (HW - 1)) & S::high());
-            n.side = (C == 0) ? ((rotl & S::even()) | (rotr & ~S::even()))
-                              : ((rotr & S::even()) | (rotl & ~S::even()));
-        }
-        return n;
-    }
-};
-
-// One bit plane of the bit-serial comparison "uniform < threshold", high bit
-// first, for the sites still tied.  k = 2 sites (cls1) compare against T_2,
-// k = 4 sites against T_4; `tb` holds the two threshold bits of this plane
-// (bit 1: T_2, bit 0: T_4) and is uniform, so each case is straight-line code.
-//   threshold bit 1: plane bit 0 -> below (accept), plane bit 1 -> still tied
-//   threshold bit 0: plane bit 1 -> above (reject), plane bit 0 -> still tied
-__device__ __forceinline__ void compare_plane(uint32_t x, uint32_t tb, uint32_t cls1, uint32_t& eq, uint32_t& acc)
-{
-    switch (tb) {
-    case 0:
-        eq &= ~x;
-        break;
-    case 3:
-        acc |= eq & ~x;
-        eq &= x;
-        break;
-    case 2:  // T_2 bit set, T_4 bit clear
-        acc |= eq & cls1 & ~x;
-        eq &= ~(x ^ cls1);
-        break;
-    default:  // T_4 bit set, T_2 bit clear
-        acc |= eq & ~cls1 & ~x;
-        eq &= x ^ cls1;
-        break;
-    }
-}
-
-// Metropolis acceptance mask of one 32-site word.  A site flips if at least two
-// of its four neighbours are anti-aligned (k = s h <= 0), else if its uniform
-// x (high 16 bits from the bit planes, low 16 bits drawn on a tie) is below
-// the threshold of its class (one anti-aligned neighbour: k = 2; none: k = 4).
-__device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_t v, uint32_t ctr1, uint32_t j,
-                                                const SweepArgs& a)
-{
-    const uint32_t d1 = w ^ n.up, d2 = w ^ n.dn, d3 = w ^ n.same, d4 = w ^ n.side;
-    const uint32_t o12 = d1 | d2, a12 = d1 & d2, o34 = d3 | d4, a34 = d3 & d4;
-    const uint32_t ge2 = a12 | a34 | (o12 & o34);
-    const uint32_t any = o12 | o34;
-    const uint32_t cls1 = any & ~ge2;  // k = 2
-    uint32_t eq = ~ge2;                // sites still tied with their threshold
-    uint32_t acc = ge2;
-    if (a.t2h > 0xFFFFu) {             // T_2 = 2^32: always accepted
-        acc |= cls1;
-        eq &= ~cls1;
-    }
-    if (a.t4h > 0xFFFFu) {
-        acc |= ~any;
-        eq &= any;
-    }
-#pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-        if (!__any(eq != 0u)) break;
-        const U4 P = philox10(4u * v + (uint32_t)kk, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
-        const uint32_t pl[4] = {P.x, P.y, P.z, P.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int bit = 15 - (4 * kk + q);
-            const uint32_t tb = (((a.t2h >> bit) & 1u) << 1) | ((a.t4h >> bit) & 1u);
-            compare_plane(pl[q], tb, cls1, eq, acc);
-        }
-    }
-    if (__any(eq != 0u)) {
-        uint32_t tie = eq;
-        while (tie) {
-            const int b = __builtin_ctz(tie);
-            tie &= tie - 1u;
-            const uint32_t q = 32u * v + (uint32_t)b;
-            const U4 P = philox10(q >> 3, ctr1, j, kStreamSweepLow, a.key0, a.key1);
-            const uint32_t word = pick(P, (q >> 1) & 3u);
-            const uint32_t lo = (q & 1u) ? (word & 0xFFFFu) : (word >> 16);
-            const uint32_t tl = ((cls1 >> b) & 1u) ? a.t2l : a.t4l;
-            if (lo < tl) acc |= 1u << b;
-        }
-    }
-    return acc;
-}
-
-template <int L, int C>
-__device__ __forceinline__ void half_sweep(uint32_t (&own)[Geo<L>::K], const uint32_t (&oth)[Geo<L>::K], int lane,
-                                           int gl, uint32_t g, uint32_t j, const SweepArgs& a)
-{
-    using Gm = Geo<L>;
-    const Neighbours<L, C> nb(oth, lane, gl);
-    const uint32_t ctr1 = 2u * g + (uint32_t)C;
-#pragma unroll
-    for (int k = 0; k < Gm::K; ++k) {
-        const uint32_t v = (uint32_t)(gl * Gm::K + k);
-        own[k] ^= accept_mask(own[k], nb.get(oth, k), v, ctr1, j, a);
-    }
-}
-
-// Sign bits of 64 consecutive int8 spins -> (even-x bits, odd-x bits).
-__device__ __forceinline__ void pack64(const uint4* src, uint32_t& ev, uint32_t& od)
-{
-    ev = 0;
-    od = 0;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint4 q = src[i];
-        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int p = 2 * (4 * i + k);
-            ev |= ((w[k] >> 7) & 1u) << p;
-            ev |= ((w[k] >> 23) & 1u) << (p + 1);
-            od |= ((w[k] >> 15) & 1u) << p;
-            od |= ((w[k] >> 31) & 1u) << (p + 1);
-        }
-    }
-}
-
-__device__ __forceinline__ void unpack64(uint32_t ev, uint32_t od, uint4* dst)
-{
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        uint32_t w[4];
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int p = 2 * (4 * i + k);
-            const uint32_t m = ((ev >> p) & 1u) * 0xFEu | ((od >> p) & 1u) * 0xFE00u |
-                               ((ev >> (p + 1)) & 1u) * 0xFE0000u | ((od >> (p + 1)) & 1u) * 0xFE000000u;
-            w[k] = 0x01010101u | m;
-        }
-        dst[i] = make_uint4(w[0], w[1], w[2], w[3]);
-    }
-}
-
-// Row-parity blend between the even-x / odd-x bits of a 64-site chunk and the
-// two colour words: colour 0 holds the even-x sites of even rows.
-template <int L>
-__device__ __forceinline__ uint32_t even_row_mask(uint32_t v)
-{
-    using Gm = Geo<L>;
-    if constexpr (Gm::WIDE) {
-        return (((v / Gm::WPR) & 1u) == 0u) ? 0xFFFFFFFFu : 0u;
-    } else {
-        return Seg<Gm::HW>::even();
-    }
-}
-
-// Replica identity of a lane: group of G lanes per replica inside the wave.
-struct LaneInfo {
-    int lane, gl;
-    uint32_t j;
-    bool valid;
-};
-
-// Initial-state word (stream INIT): the INIT output word p >> 5 with
-// p = c N/2 + q is exactly the 32-site word (c, v) of the bit store.
-template <int L>
-__device__ __forceinline__ uint32_t init_word(int c, uint32_t v, uint32_t j, const SweepArgs& a)
-{
-    const uint32_t idx = (uint32_t)(c * Geo<L>::NW) + v;
-    return pick(philox10(idx >> 2, 0u, j, kStreamInit, a.key0, a.key1), idx & 3u);
-}
-
-// Load the colour-0 / colour-1 words of word index v of replica j.
-template <int L, bool INT8>
-__device__ __forceinline__ void load_word(const SweepArgs& a, uint32_t j, uint32_t v, uint32_t& w0, uint32_t& w1)
-{
-    using Gm = Geo<L>;
-    if constexpr (INT8) {
-        const uint4* base = reinterpret_cast<const uint4*>(a.spin + (size_t)j * Gm::N);
-        uint32_t ev, od;
-        pack64(base + 4 * v, ev, od);
-        const uint32_t em = even_row_mask<L>(v);
-        w0 = (ev & em) | (od & ~em);
-        w1 = (od & em) | (ev & ~em);
-    } else {
-        const uint32_t* base = reinterpret_cast<const uint32_t*>(a.spin + (size_t)j * Gm::BITS_BYTES);
-        w0 = base[v];
-        w1 = base[Gm::NW + v];
-    }
-}
-
-template <int L, bool INT8>
-__device__ __forceinline__ void store_word(const SweepArgs& a, uint32_t j, uint32_t v, uint32_t w0, uint32_t w1)
-{
-    using Gm = Geo<L>;
-    if constexpr (INT8) {
-        uint4* base = reinterpret_cast<uint4*>(a.spin + (size_t)j * Gm::N);
-        const uint32_t em = even_row_mask<L>(v);
-        unpack64((w0 & em) | (w1 & ~em), (w1 & em) | (w0 & ~em), base + 4 * v);
-    } else {
-        uint32_t* base = reinterpret_cast<uint32_t*>(a.spin + (size_t)j * Gm::BITS_BYTES);
-        base[v] = w0;
-        base[Gm::NW + v] = w1;
-    }
-}
-
-// E = 2 (anti-aligned bonds) - 2N and M = N - 2 (down spins), written by the
-// first lane of the replica's group.
-template <int L>
-__device__ __forceinline__ void write_EM(const SweepArgs& a, const LaneInfo& li, uint32_t anti, uint32_t downs)
-{
-    using Gm = Geo<L>;
-#pragma unroll
-    for (int off = Gm::G / 2; off >= 1; off >>= 1) {
-        anti += (uint32_t)__shfl_xor((int)anti, off);
-        downs += (uint32_t)__shfl_xor((int)downs, off);
-    }
-    if (li.valid && li.gl == 0) {
-        a.E[li.j] = 2 * (int32_t)anti - 2 * Gm::N;
-        a.M[li.j] = Gm::N - 2 * (int32_t)downs;
-    }
-}
-
-// Register-resident sweep: each lane owns one word per colour (L <= 64).
-template <int L, bool INT8>
-__device__ __forceinline__ void sweep_regs(const SweepArgs& a, const LaneInfo& li)
-{
-    using Gm = Geo<L>;
-    static_assert(Gm::K == 1, "one word per lane");
-    const uint32_t v = (uint32_t)li.gl;
-    uint32_t s0[1], s1[1];
-    if (a.init) {
-        s0[0] = init_word<L>(0, v, li.j, a);
-        s1[0] = init_word<L>(1, v, li.j, a);
-    } else if (li.valid) {
-        load_word<L, INT8>(a, li.j, v, s0[0], s1[0]);
-    } else {
-        s0[0] = s1[0] = 0u;
-    }
-    for (int t = 0; t < a.nsweeps; ++t) {
-        const uint32_t g = a.g0 + (uint32_t)t;
-        half_sweep<L, 0>(s0, s1, li.lane, li.gl, g, li.j, a);
-        half_sweep<L, 1>(s1, s0, li.lane, li.gl, g, li.j, a);
-    }
-    const Neighbours<L, 0> nb(s1, li.lane, li.gl);
-    const Nb n = nb.get(s1, 0);
-    const uint32_t anti = __popc(s0[0] ^ n.up) + __popc(s0[0] ^ n.dn) + __popc(s0[0] ^ n.same) + __popc(s0[0] ^ n.side);
-    const uint32_t downs = __popc(s0[0]) + __popc(s1[0]);
-    write_EM<L>(a, li, anti, downs);
-    if (li.valid) store_word<L, INT8>(a, li.j, v, s0[0], s1[0]);
-}
-
-// LDS-resident sweep for rows of whole words (L >= 128): one wave per block
-// owns one replica; word (k, lane) of a colour sits at k * 64 + lane, so the
-// 64 lanes touch 64 consecutive words for every k.
-template <int L>
-struct LdsRep {
-    using Gm = Geo<L>;
-    static constexpr int K = Gm::K, WPR = Gm::WPR, RL = Gm::RL;
-    uint32_t* w;  // [2][NW]
-    __device__ __forceinline__ uint32_t& at(int c, int k, int gl) const { return w[c * Gm::NW + k * 64 + gl]; }
-    // neighbour words (other colour 1 - C) of own word k of lane gl
-    template <int C>
-    __device__ __forceinline__ Nb nb(int k, int gl) const
-    {
-        constexpr int O = 1 - C;
-        const int r = k / WPR, t = k - (k / WPR) * WPR;
-        Nb n;
-        n.same = at(O, k, gl);
-        n.up = (r > 0) ? at(O, k - WPR, gl) : at(O, (RL - 1) * WPR + t, (gl + 63) & 63);
-        n.dn = (r < RL - 1) ? at(O, k + WPR, gl) : at(O, t, (gl + 1) & 63);
-        if (((r + C) & 1) == 0) {  // RL is even: row parity is the parity of r
-            const int tp = (t == 0) ? WPR - 1 : t - 1;
-            n.side = __builtin_amdgcn_alignbit(n.same, at(O, r * WPR + tp, gl), 31);
-        } else {
-            const int tn = (t == WPR - 1) ? 0 : t + 1;
-            n.side = __builtin_amdgcn_alignbit(at(O, r * WPR + tn, gl), n.same, 1);
-        }
-        return n;
-    }
-};
-
-template <int L, bool INT8, int C>
-__device__ __forceinline__ void half_sweep_lds(const LdsRep<L>& rep, int gl, uint32_t g, uint32_t j, const SweepArgs& a)
-{
-    const uint32_t ctr1 = 2u * g + (uint32_t)C;
-#pragma unroll 1
-    for (int k = 0; k < Geo<L>::K; ++k) {
-        const uint32_t v = (uint32_t)(gl * Geo<L>::K + k);
-        const Nb n = rep.template nb<C>(k, gl);
-        uint32_t& own = rep.at(C, k, gl);
-        own ^= accept_mask(own, n, v, ctr1, j, a);
-    }
-    __syncthreads();
-}
-
-template <int L, bool INT8>
-__device__ __forceinline__ void sweep_lds(const SweepArgs& a, const LaneInfo& li, uint32_t* lds)
-{
-    using Gm = Geo<L>;
-    static_assert(Gm::WIDE && Gm::RL % 2 == 0 && Gm::G == 64, "LDS path layout");
-    const LdsRep<L> rep{lds};
-    const int gl = li.gl;
-#pragma unroll 1
-    for (int k = 0; k < Gm::K; ++k) {
-        const uint32_t v = (uint32_t)(gl * Gm::K + k);
-        uint32_t w0, w1;
-        if (a.init) {
-            w0 = init_word<L>(0, v, li.j, a);
-            w1 = init_word<L>(1, v, li.j, a);
-        } else {
-            load_word<L, INT8>(a, li.j, v, w0, w1);
-        }
-        rep.at(0, k, gl) = w0;
-        rep.at(1, k, gl) = w1;
-    }
-    __syncthreads();
-    for (int t = 0; t < a.nsweeps; ++t) {
-        const uint32_t g = a.g0 + (uint32_t)t;
-        half_sweep_lds<L, INT8, 0>(rep, gl, g, li.j, a);
-        half_sweep_lds<L, INT8, 1>(rep, gl, g, li.j, a);
-    }
-    uint32_t anti = 0, downs = 0;
-#pragma unroll 1
-    for (int k = 0; k < Gm::K; ++k) {
-        const Nb n = rep.template nb<0>(k, gl);
-        const uint32_t w0 = rep.at(0, k, gl), w1 = rep.at(1, k, gl);
-        anti += __popc(w0 ^ n.up) + __popc(w0 ^ n.dn) + __popc(w0 ^ n.same) + __popc(w0 ^ n.side);
-        downs += __popc(w0) + __popc(w1);
-        store_word<L, INT8>(a, li.j, (uint32_t)(gl * Gm::K + k), w0, w1);
-    }
-    write_EM<L>(a, li, anti, downs);
-}
-
-template <int L>
-constexpr int sweep_block()
-{
-    return Geo<L>::K == 1 ? kBlock : 64;
-}
+using namespace pa::dev;
 
 template <int L, bool INT8>
 __global__ __launch_bounds__(sweep_block<L>()) void sweep_kernel(SweepArgs a)
@@ -526,20 +50,6 @@ __global__ __launch_bounds__(sweep_block<L>()) void sweep_kernel(SweepArgs a)
 // the exact sums of E, E^2, |M|, M^2 (int64) and M^4 (128 bit).  Integer
 // atomics only, so the result does not depend on scheduling order.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void add_u128(uint64_t& lo, uint64_t& hi, uint64_t blo, uint64_t bhi)
-{
-    const uint64_t s = lo + blo;
-    hi += bhi + (s < lo ? 1u : 0u);
-    lo = s;
-}
-
-__device__ __forceinline__ void atomic_add_u128(uint64_t* lo_p, uint64_t* hi_p, uint64_t lo, uint64_t hi)
-{
-    const uint64_t old = atomicAdd((unsigned long long*)lo_p, (unsigned long long)lo);
-    const uint64_t carry = (old + lo < old) ? 1u : 0u;
-    if (hi + carry) atomicAdd((unsigned long long*)hi_p, (unsigned long long)(hi + carry));
-}
-
 __global__ __launch_bounds__(kBlock) void stats_kernel(const int32_t* __restrict__ E, const int32_t* __restrict__ M,
                                                        int32_t n, int32_t N, DevStats* st, uint32_t* hist,
                                                        int32_t nbins, int record, DevMhr mhr)
@@ -613,29 +123,6 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t value, size_t n)
 // Resampling: copy counts (one RESAMPLE uniform per parent), block sums,
 // exclusive scan, parent index per child, replica copy.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* total)
-{
-    __shared__ uint32_t wsum[kBlock / 64];
-    const int lane = (int)(threadIdx.x & 63u), wid = (int)(threadIdx.x >> 6);
-    uint32_t incl = x;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = (uint32_t)__shfl_up((int)incl, off);
-        if (lane >= off) incl += y;
-    }
-    if (lane == 63) wsum[wid] = incl;
-    __syncthreads();
-    uint32_t before = 0, all = 0;
-#pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) {
-        if (w < wid) before += wsum[w];
-        all += wsum[w];
-    }
-    __syncthreads();
-    *total = all;
-    return before + incl - x;
-}
-
 __global__ __launch_bounds__(kBlock) void counts_kernel(const int32_t* __restrict__ E, int32_t n, int32_t N,
                                                         int32_t bmin, int32_t nwin, const uint32_t* __restrict__ tbl,
                                                         uint32_t step, uint32_t key0, uint32_t key1,
