@@ -245,8 +245,61 @@ pa_status pa_batch_reweight(pa_batch* b, int32_t run, const double* betas, int32
 /* Population of one run as int8 +-1 row-major spins and E, M (test hook). */
 pa_status pa_batch_download_population(pa_batch* b, int32_t run, int8_t* spins, int32_t* E, int32_t* M);
 
+/* Load the learned proposer used by PA_STEP_LEARNED runs: params[4801] FP32
+ * MLP weights and norm[18] normalisation constants (layout below).  The batch
+ * keeps a BF16 copy; inference runs on the device after every step. */
+pa_status pa_batch_set_model(pa_batch* b, const float* params, const float* norm);
+
+/* Training pairs logged by the bisection of adaptive (and learned-fallback)
+ * steps of all runs: x[k][8] features, t[k] = ln(beta_{i+1} - beta_i).
+ * Copies min(cap, count) pairs; *n receives the count. */
+pa_status pa_batch_training_pairs(const pa_batch* b, float* x, float* t, int32_t cap, int32_t* n);
+
+/* Features x[8] of one run's population after its last step, whether they are
+ * valid, and the model's proposal (ln step) made from them (test hook). */
+pa_status pa_batch_features(const pa_batch* b, int32_t run, float* x, int32_t* valid, float* prop);
+
+/* Learned mode: proposals made and accepted by the exact overlap test. */
+pa_status pa_batch_learned_stats(const pa_batch* b, int32_t run, int32_t* proposals, int32_t* accepted);
+
 /* Release the batch handle (the caller frees the workspace). */
 pa_status pa_batch_free(pa_batch* b);
+
+/* ---- Learned temperature-step proposer -------------------------------------
+ * A small MLP 8 -> 64 -> 64 -> 1 (ReLU) maps features of the population's
+ * energy histogram to the natural log of the step size the overlap bisection
+ * of Sec. 2.3 would choose.  Features: e/N, ln sigma_E, skewness, excess
+ * kurtosis of the energy distribution, beta, ln L, ln R, ln(last step).
+ * Parameters (FP32, 4801): W1[64][8] b1[64] W2[64][64] b2[64] w3[64] b3.
+ * Normalisation (18): feature means[8], feature std devs[8], target mean, std.
+ * Training: mean squared error on the normalised target, minibatch SGD with
+ * momentum, all on the device with a deterministic gradient reduction. */
+#define PA_MLP_PARAMS 4801
+#define PA_MLP_NORM 18
+
+typedef struct pa_mlp pa_mlp;
+
+size_t pa_mlp_workspace_bytes(int32_t max_batch);
+
+/* Network with He-initialised weights drawn from `seed` and identity
+ * normalisation; max_batch bounds the minibatch and gradient sizes. */
+pa_status pa_mlp_create(int32_t max_batch, uint64_t seed, void* d_workspace, size_t bytes, void* hip_stream,
+                        pa_mlp** out);
+pa_status pa_mlp_set_params(pa_mlp* m, const float* params, const float* norm);  /* host arrays; either may be NULL */
+pa_status pa_mlp_get_params(pa_mlp* m, float* params, float* norm);
+/* Normalisation from n raw samples (device arrays x[n][8], t[n]). */
+pa_status pa_mlp_fit_norm(pa_mlp* m, const float* d_x, const float* d_t, int32_t n);
+/* y[k] = network(x[k]) for n raw feature vectors (device arrays), de-normalised;
+ * bf16 != 0 uses the BF16 inference path, else the FP32 master weights. */
+pa_status pa_mlp_forward(pa_mlp* m, const float* d_x, int32_t n, float* d_y, int32_t bf16);
+/* Gradient (host grad[4801]) and loss of the n <= max_batch samples. */
+pa_status pa_mlp_gradient(pa_mlp* m, const float* d_x, const float* d_t, int32_t n, float* grad, float* loss);
+/* `epochs` passes of minibatch SGD (shuffled with `seed`, full minibatches of
+ * `batch` samples); epoch_loss[epochs] (may be NULL) receives the mean loss. */
+pa_status pa_mlp_train(pa_mlp* m, const float* d_x, const float* d_t, int32_t n, int32_t batch, int32_t epochs,
+                       float lr, float momentum, uint64_t seed, float* epoch_loss);
+const char* pa_mlp_last_error(const pa_mlp* m);
+pa_status pa_mlp_free(pa_mlp* m);
 
 #ifdef __cplusplus
 }

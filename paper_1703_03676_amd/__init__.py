@@ -107,7 +107,24 @@ SIGNATURES = {
     "pa_batch_reweight": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_double), ctypes.c_int32, _P(Obs)]),
     "pa_batch_download_population": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _vp, _vp]),
     "pa_batch_free": (ctypes.c_int, [_vp]),
+    "pa_batch_set_model": (ctypes.c_int, [_vp, _vp, _vp]),
+    "pa_batch_training_pairs": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _P(ctypes.c_int32)]),
+    "pa_batch_features": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _P(ctypes.c_int32), _P(ctypes.c_float)]),
+    "pa_batch_learned_stats": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_int32)]),
+    "pa_mlp_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+    "pa_mlp_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_uint64, _vp, ctypes.c_size_t, _vp, _P(_vp)]),
+    "pa_mlp_set_params": (ctypes.c_int, [_vp, _vp, _vp]),
+    "pa_mlp_get_params": (ctypes.c_int, [_vp, _vp, _vp]),
+    "pa_mlp_fit_norm": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32]),
+    "pa_mlp_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, ctypes.c_int32]),
+    "pa_mlp_gradient": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _vp, _P(ctypes.c_float)]),
+    "pa_mlp_train": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_uint64, _vp]),
+    "pa_mlp_last_error": (ctypes.c_char_p, [_vp]),
+    "pa_mlp_free": (ctypes.c_int, [_vp]),
 }
+
+MLP_PARAMS, MLP_NORM = 4801, 18
 
 _lib = None
 
@@ -322,6 +339,32 @@ class Batch:
         _check(lib().pa_batch_reweight(self.h, int(run), betas.ctypes.data_as(_P(ctypes.c_double)), len(betas), out))
         return [out[k].as_dict() for k in range(len(betas))]
 
+    def set_model(self, params, norm):
+        params = np.ascontiguousarray(params, dtype=np.float32)
+        norm = np.ascontiguousarray(norm, dtype=np.float32)
+        assert params.shape == (MLP_PARAMS,) and norm.shape == (MLP_NORM,)
+        _check(lib().pa_batch_set_model(self.h, _ptr(params), _ptr(norm)))
+
+    def training_pairs(self):
+        n = ctypes.c_int32()
+        _check(lib().pa_batch_training_pairs(self.h, None, None, 0, ctypes.byref(n)))
+        x = np.empty((max(n.value, 1), 8), np.float32)
+        t = np.empty(max(n.value, 1), np.float32)
+        _check(lib().pa_batch_training_pairs(self.h, _ptr(x), _ptr(t), n.value, ctypes.byref(n)))
+        return x[: n.value], t[: n.value]
+
+    def features(self, run):
+        x = np.empty(8, np.float32)
+        v = ctypes.c_int32()
+        pr = ctypes.c_float()
+        _check(lib().pa_batch_features(self.h, int(run), _ptr(x), ctypes.byref(v), ctypes.byref(pr)))
+        return x, bool(v.value), pr.value
+
+    def learned_stats(self, run):
+        p, a = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().pa_batch_learned_stats(self.h, int(run), ctypes.byref(p), ctypes.byref(a)))
+        return p.value, a.value
+
     def download_population(self, run):
         L = self.specs[run]["L"]
         n = self.state(run)["R"]
@@ -330,6 +373,78 @@ class Batch:
         M = np.empty(n, np.int32)
         _check(lib().pa_batch_download_population(self.h, int(run), _ptr(s), _ptr(E), _ptr(M)))
         return s, E, M
+
+
+class Mlp:
+    """The learned step proposer (MLP 8 -> 64 -> 64 -> 1) with its device
+    training and inference kernels.  Data arguments are torch CUDA tensors."""
+
+    def __init__(self, max_batch=1024, seed=0, stream=None, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU available: libpa runs on the GPU only")
+        nbytes = lib().pa_mlp_workspace_bytes(int(max_batch))
+        if nbytes == 0:
+            raise PaError(PA_EINVAL, "invalid max_batch")
+        dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(dev)
+        self.max_batch = int(max_batch)
+        h = ctypes.c_void_p()
+        _check(lib().pa_mlp_create(self.max_batch, int(seed), ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
+                                   ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pa_mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def _err(self, st):
+        if st != PA_OK:
+            raise PaError(st, strerror(st) + ": " + lib().pa_mlp_last_error(self.h).decode())
+
+    @staticmethod
+    def _dev(t):
+        import torch
+        assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+        return ctypes.c_void_p(t.data_ptr())
+
+    def params(self):
+        p = np.empty(MLP_PARAMS, np.float32)
+        n = np.empty(MLP_NORM, np.float32)
+        self._err(lib().pa_mlp_get_params(self.h, _ptr(p), _ptr(n)))
+        return p, n
+
+    def set_params(self, params=None, norm=None):
+        p = None if params is None else np.ascontiguousarray(params, dtype=np.float32)
+        n = None if norm is None else np.ascontiguousarray(norm, dtype=np.float32)
+        self._err(lib().pa_mlp_set_params(self.h, None if p is None else _ptr(p), None if n is None else _ptr(n)))
+
+    def fit_norm(self, x, t):
+        self._err(lib().pa_mlp_fit_norm(self.h, self._dev(x), self._dev(t), int(x.shape[0])))
+
+    def forward(self, x, bf16=True):
+        import torch
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        self._err(lib().pa_mlp_forward(self.h, self._dev(x), int(x.shape[0]), self._dev(y), 1 if bf16 else 0))
+        return y
+
+    def gradient(self, x, t):
+        g = np.empty(MLP_PARAMS, np.float32)
+        loss = ctypes.c_float()
+        self._err(lib().pa_mlp_gradient(self.h, self._dev(x), self._dev(t), int(x.shape[0]), _ptr(g),
+                                        ctypes.byref(loss)))
+        return g, loss.value
+
+    def train(self, x, t, batch=256, epochs=10, lr=1e-2, momentum=0.9, seed=0):
+        losses = np.empty(max(int(epochs), 1), np.float32)
+        self._err(lib().pa_mlp_train(self.h, self._dev(x), self._dev(t), int(x.shape[0]), int(batch), int(epochs),
+                                     float(lr), float(momentum), int(seed), _ptr(losses)))
+        return losses[: int(epochs)]
 
 
 def default_capacity(R):

@@ -36,6 +36,7 @@
 #include "pa.h"
 #include "pa_device.h"
 #include "pa_host.h"
+#include "pa_mlp_dev.h"
 
 namespace pa {
 namespace batch {
@@ -70,6 +71,25 @@ struct StepDev {
     uint32_t t2h, t2l, t4h, t4l;
     int32_t bmin, nwin;
     uint32_t tbl_off;  // offset in u32 of this run's tables in the table area
+    int32_t pad;
+    double beta;        // inverse temperature after this step
+    double last_dbeta;  // the step just taken (0: none)
+};
+
+// Features of the population after a step and the learned proposal for the
+// next step (natural log of the step size).
+struct FeatDev {
+    float x[8];
+    float prop;
+    int32_t valid;
+};
+
+// Learned proposer as used by the batch: BF16 weights and normalisation.
+struct ModelDev {
+    int32_t set;
+    int32_t pad[3];
+    float norm[pa::mlp::kNorm];
+    __hip_bfloat16 wb[pa::mlp::kParams];
 };
 
 struct ResultDev {
@@ -320,6 +340,72 @@ __global__ __launch_bounds__(kBlock) void b_stats(const Item* __restrict__ items
     }
 }
 
+// One block of 64 threads per run: energy moments of the measured population
+// from its histogram (FP64, fixed-order reduction), the proposer's features,
+// and -- when a model is loaded -- the BF16 proposal for the next step:
+//   x = (e/N, ln sigma_E, skew, excess kurtosis, beta, ln L, ln R, ln last step).
+__global__ __launch_bounds__(64) void b_features(const RunDev* __restrict__ runs, const StepDev* __restrict__ steps,
+                                                 const ResultDev* __restrict__ res, const ModelDev* __restrict__ model,
+                                                 FeatDev* __restrict__ feats)
+{
+    __shared__ double red[3][64];
+    __shared__ float h[pa::mlp::kHid];
+    __shared__ float xs[8];
+    const StepDev st = steps[blockIdx.x];
+    if (!st.active) return;
+    int buf, n;
+    const bool ok = post_resample(st, res[blockIdx.x], &buf, &n);
+    const RunDev& rd = runs[blockIdx.x];
+    const DevStats* sp = rd.stats;
+    const int t = (int)threadIdx.x;
+    const double mean = (double)(int64_t)sp->sumE / (double)n;
+    const int bmin = (sp->emin + 2 * rd.N) / 4, bmax = (sp->emax + 2 * rd.N) / 4;
+    double a2 = 0.0, a3 = 0.0, a4 = 0.0;
+    for (int b = bmin + t; b <= bmax; b += 64) {
+        const uint32_t c = rd.hist[b];
+        if (c == 0) continue;
+        const double d = (double)(4 * b - 2 * rd.N) - mean;
+        const double d2 = d * d;
+        a2 += c * d2;
+        a3 += c * d2 * d;
+        a4 += c * d2 * d2;
+    }
+    red[0][t] = a2;
+    red[1][t] = a3;
+    red[2][t] = a4;
+    __syncthreads();
+    for (int off = 32; off >= 1; off >>= 1) {
+        if (t < off) {
+            red[0][t] += red[0][t + off];
+            red[1][t] += red[1][t + off];
+            red[2][t] += red[2][t + off];
+        }
+        __syncthreads();
+    }
+    const double var = red[0][0] / n;
+    const bool valid = ok && var > 0.0 && st.last_dbeta > 0.0;
+    if (t == 0) {
+        FeatDev& f = feats[blockIdx.x];
+        const double sd = var > 0.0 ? sqrt(var) : 1.0;
+        xs[0] = (float)(mean / rd.N);
+        xs[1] = (float)log(sd);
+        xs[2] = (float)(red[1][0] / n / (sd * sd * sd));
+        xs[3] = (float)(red[2][0] / n / (var * var) - 3.0);
+        xs[4] = (float)st.beta;
+        xs[5] = (float)log((double)rd.L);
+        xs[6] = (float)log((double)rd.R);
+        xs[7] = st.last_dbeta > 0.0 ? (float)log(st.last_dbeta) : 0.0f;
+        for (int k = 0; k < 8; ++k) f.x[k] = xs[k];
+        f.valid = valid ? 1 : 0;
+        f.prop = 0.0f;
+    }
+    __syncthreads();
+    if (valid && model->set) {
+        const float y = pa::mlp::forward_bf16(xs, model->wb, model->norm, h, t);
+        if (t == 0) feats[blockIdx.x].prop = y;
+    }
+}
+
 __global__ void b_fill_u32(uint32_t* p, uint32_t value, size_t n)
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -368,7 +454,7 @@ struct RunLayout {
 
 struct BatchLayout {
     std::vector<RunLayout> runs;
-    size_t rundev, steps, results, download, tables, items, total;
+    size_t rundev, steps, results, feats, download, tables, items, model, total;
     size_t download_bytes;  // results + all stats blocks and histograms
     size_t steps_bytes;     // step descriptors + table area
     size_t n_items;
@@ -388,7 +474,7 @@ bool make_batch_layout(const pa_params* runs, int nruns, BatchLayout* bl)
         return at;
     };
     bl->runs.resize((size_t)nruns);
-    size_t dl = align_up(sizeof(ResultDev) * (size_t)nruns);
+    size_t dl = align_up(sizeof(ResultDev) * (size_t)nruns) + align_up(sizeof(FeatDev) * (size_t)nruns);
     size_t tbl = 0;
     for (int r = 0; r < nruns; ++r) {
         const pa_params& p = runs[r];
@@ -418,7 +504,9 @@ bool make_batch_layout(const pa_params* runs, int nruns, BatchLayout* bl)
     bl->rundev = take(sizeof(RunDev) * (size_t)nruns);
     bl->steps = take(bl->steps_bytes);
     bl->download = take(dl);
-    bl->results = bl->download;  // results lead the download area
+    bl->results = bl->download;  // results lead the download area, then the features
+    bl->feats = bl->download + align_up(sizeof(ResultDev) * (size_t)nruns);
+    bl->model = take(sizeof(ModelDev));
     // items: parents/statistics, copy chunks, and sweep items of every candidate shape
     size_t n_items = 0;
     for (int r = 0; r < nruns; ++r) {
@@ -536,6 +624,10 @@ struct RunHost {
     std::vector<double> w;  // scratch
     DevStats h_stats;
     const uint32_t* h_hist = nullptr;
+    FeatDev feat;
+    double last_dbeta = 0.0;
+    int32_t proposals = 0, accepted = 0;
+    std::vector<float> pair_x, pair_t;  // (features, ln step) from the bisection
 };
 
 struct pa_batch {
@@ -550,6 +642,9 @@ struct pa_batch {
     StepDev* d_steps = nullptr;
     uint32_t* d_tables = nullptr;
     ResultDev* d_results = nullptr;
+    FeatDev* d_feats = nullptr;
+    ModelDev* d_model = nullptr;
+    bool model_set = false;
     uint8_t* d_download = nullptr;
     Item* d_items = nullptr;
     // items: parents, copy, and sweep items per group
@@ -654,6 +749,9 @@ pa_status enqueue_step(pa_batch* b)
     hipLaunchKernelGGL(b_stats, dim3((unsigned)b->n_parent_items), dim3(kBlock), 0, s, items + b->parent_off,
                        b->d_rundev, b->d_steps, b->d_results);
     BCHK(hipGetLastError());
+    hipLaunchKernelGGL(b_features, dim3((unsigned)b->nruns), dim3(64), 0, s, b->d_rundev, b->d_steps, b->d_results,
+                       b->d_model, b->d_feats);
+    BCHK(hipGetLastError());
     BCHK(hipMemcpyAsync(b->h_download, b->d_download, b->lo.download_bytes, hipMemcpyDeviceToHost, s));
     return PA_OK;
 }
@@ -680,6 +778,8 @@ void read_stats(pa_batch* b, int r)
     const RunLayout& rl = b->lo.runs[(size_t)r];
     std::memcpy(&h.h_stats, b->h_download + rl.stats_off, sizeof(DevStats));
     h.h_hist = reinterpret_cast<const uint32_t*>(b->h_download + rl.stats_off + sizeof(DevStats));
+    std::memcpy(&h.feat, b->h_download + (b->lo.feats - b->lo.download) + sizeof(FeatDev) * (size_t)r,
+                sizeof(FeatDev));
 }
 
 void record_measurement(RunHost& h)
@@ -695,7 +795,11 @@ void record_measurement(RunHost& h)
 }
 
 // Next inverse temperature of a run, or false (with the run's status set).
-bool choose_beta(RunHost& h, const host::Hist& hw, double* beta_next)
+// Learned mode: the proposal beta + exp(prop) is accepted when the exact
+// overlap is within alpha_tol of the target (or it reaches beta_f with enough
+// overlap); otherwise the bisection decides.  Every interior bisection root is
+// logged as a training pair (features, ln step).
+bool choose_beta(RunHost& h, const host::Hist& hw, bool model_set, double* beta_next)
 {
     const pa_schedule& s = h.sched;
     if (s.mode == PA_STEP_FIXED) {
@@ -705,10 +809,29 @@ bool choose_beta(RunHost& h, const host::Hist& hw, double* beta_next)
         if (*beta_next > s.beta_f) *beta_next = s.beta_f;
         return true;
     }
+    if (s.mode == PA_STEP_LEARNED && model_set && h.feat.valid) {
+        const double d = std::exp((double)h.feat.prop);
+        if (std::isfinite(d) && d > 0.0) {
+            const double bp = std::min(h.beta + d, s.beta_f);
+            if (bp > h.beta) {
+                const double a = host::overlap(hw, h.p.R, h.R_cur, bp - h.beta, h.w);
+                h.proposals += 1;
+                if (std::fabs(a - s.alpha_star) <= s.alpha_tol || (bp == s.beta_f && a >= s.alpha_star)) {
+                    h.accepted += 1;
+                    *beta_next = bp;
+                    return true;
+                }
+            }
+        }
+    }
     double a = 0.0;
     if (!host::adapt_beta(hw, h.p.R, h.R_cur, h.beta, s.beta_f, s.alpha_star, beta_next, &a, h.w)) {
         h.status = PA_EINVAL;
         return false;
+    }
+    if (*beta_next < s.beta_f && h.feat.valid) {
+        h.pair_x.insert(h.pair_x.end(), h.feat.x, h.feat.x + 8);
+        h.pair_t.push_back((float)std::log(*beta_next - h.beta));
     }
     return true;
 }
@@ -772,6 +895,8 @@ static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int
     b->d_tables = reinterpret_cast<uint32_t*>(ws + bl.tables);
     b->d_download = ws + bl.download;
     b->d_results = reinterpret_cast<ResultDev*>(ws + bl.results);
+    b->d_feats = reinterpret_cast<FeatDev*>(ws + bl.feats);
+    b->d_model = reinterpret_cast<ModelDev*>(ws + bl.model);
     b->d_items = reinterpret_cast<Item*>(ws + bl.items);
     b->runs.resize((size_t)nruns);
     b->rundev.resize((size_t)nruns);
@@ -811,6 +936,12 @@ static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int
         hipHostMalloc((void**)&b->h_download, bl.download_bytes, hipHostMallocDefault) != hipSuccess)
         return PA_ENOMEM;
     std::memset(b->h_steps, 0, bl.steps_bytes);
+    {
+        ModelDev md;
+        std::memset(&md, 0, sizeof(md));
+        BCHK(hipMemcpyAsync(b->d_model, &md, sizeof(md), hipMemcpyHostToDevice, b->stream));
+        BCHK(hipStreamSynchronize(b->stream));
+    }
     BCHK(hipMemcpyAsync(b->d_rundev, b->rundev.data(), sizeof(RunDev) * (size_t)nruns, hipMemcpyHostToDevice,
                         b->stream));
     for (int r = 0; r < nruns; ++r) {
@@ -911,7 +1042,7 @@ pa_status pa_batch_step(pa_batch* b, int32_t* n_active)
         if (h.finished || h.status != PA_OK) return;
         const host::Hist hw = host::hist_window(h.h_hist, h.h_stats, h.p.L * h.p.L);
         double bn = 0.0;
-        if (!choose_beta(h, hw, &bn)) return;
+        if (!choose_beta(h, hw, b->model_set, &bn)) return;
         h.beta_next = bn;
         h.stepping = true;
     });
@@ -948,6 +1079,8 @@ pa_status pa_batch_step(pa_batch* b, int32_t* n_active)
         d.bmin = hw.bmin;
         d.nwin = hw.bmax - hw.bmin + 1;
         d.tbl_off = toff[(size_t)r];
+        d.beta = bn;
+        d.last_dbeta = bn - h.beta;
     });
     if (any) {
         const pa_status st = replay(b, (b->lo.tables - b->lo.steps) + (size_t)o * 4);
@@ -966,6 +1099,7 @@ pa_status pa_batch_step(pa_batch* b, int32_t* n_active)
             h.R_cur = res[r].r_new;
             h.step += 1;
             h.sweeps += (uint64_t)h.sched.theta;
+            h.last_dbeta = h.beta_next - h.beta;
             h.beta = h.beta_next;
             h.lnZ += h.lnQ_next;
             h.lnQ_last = h.lnQ_next;
@@ -1057,6 +1191,56 @@ pa_status pa_batch_download_population(pa_batch* b, int32_t run, int8_t* spins, 
         }
     }
     BCHK(hipStreamSynchronize(b->stream));
+    return PA_OK;
+}
+
+pa_status pa_batch_set_model(pa_batch* b, const float* params, const float* norm)
+{
+    if (!b || !params || !norm) return PA_EINVAL;
+    if (b->broken) return PA_ESTATE;
+    ModelDev md;
+    std::memset(&md, 0, sizeof(md));
+    md.set = 1;
+    for (int k = 0; k < pa::mlp::kNorm; ++k) md.norm[k] = norm[k];
+    for (int q = 0; q < pa::mlp::kParams; ++q) md.wb[q] = __float2bfloat16(params[q]);
+    BCHK(hipMemcpyAsync(b->d_model, &md, sizeof(md), hipMemcpyHostToDevice, b->stream));
+    BCHK(hipStreamSynchronize(b->stream));
+    b->model_set = true;
+    return PA_OK;
+}
+
+pa_status pa_batch_training_pairs(const pa_batch* b, float* x, float* t, int32_t cap, int32_t* n)
+{
+    if (!b || !n || cap < 0 || (cap > 0 && (!x || !t))) return PA_EINVAL;
+    int32_t k = 0;
+    for (const RunHost& h : b->runs) {
+        for (size_t i = 0; i < h.pair_t.size(); ++i) {
+            if (k < cap) {
+                std::memcpy(x + (size_t)k * 8, h.pair_x.data() + i * 8, 8 * sizeof(float));
+                t[k] = h.pair_t[i];
+            }
+            ++k;
+        }
+    }
+    *n = k;
+    return PA_OK;
+}
+
+pa_status pa_batch_features(const pa_batch* b, int32_t run, float* x, int32_t* valid, float* prop)
+{
+    if (!b || run < 0 || run >= b->nruns || !x || !valid || !prop) return PA_EINVAL;
+    const FeatDev& f = b->runs[(size_t)run].feat;
+    std::memcpy(x, f.x, sizeof(f.x));
+    *valid = f.valid;
+    *prop = f.prop;
+    return PA_OK;
+}
+
+pa_status pa_batch_learned_stats(const pa_batch* b, int32_t run, int32_t* proposals, int32_t* accepted)
+{
+    if (!b || run < 0 || run >= b->nruns || !proposals || !accepted) return PA_EINVAL;
+    *proposals = b->runs[(size_t)run].proposals;
+    *accepted = b->runs[(size_t)run].accepted;
     return PA_OK;
 }
 

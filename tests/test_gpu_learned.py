@@ -1,0 +1,105 @@
+"""Learned temperature steps: pairs logged by the bisection of adaptive runs
+train the proposer on the GPU; learned runs then mostly skip the bisection
+(the exact overlap test accepts the proposal) and reach the same free-energy
+accuracy against the exact finite-torus result as plain adaptive runs."""
+import time
+
+import numpy as np
+import pytest
+
+import exact
+
+pa = pytest.importorskip("paper_1703_03676_amd")
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+ALPHA, THETA, BF = 0.85, 5, 1.0
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _runs(seeds):
+    return [dict(L=16 if s % 2 else 32, R=1000, seed=int(s), layout="bits") for s in seeds]
+
+
+@pytest.fixture(scope="module")
+def trained():
+    print("case learned: collect and train", flush=True)
+    b = pa.Batch(_runs(range(1, 25)), dict(beta_f=BF, alpha_star=ALPHA, theta=THETA, mode="adaptive"))
+    b.run()
+    x, t = b.training_pairs()
+    assert len(t) > 500 and np.all(np.isfinite(x)) and np.all(np.isfinite(t))
+    m = pa.Mlp(max_batch=256, seed=0)
+    xc, tc = torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda()
+    m.fit_norm(xc, tc)
+    losses = m.train(xc, tc, batch=64, epochs=300, lr=3e-3, momentum=0.9, seed=1)
+    assert losses[-1] < 0.2 * losses[0]
+    params, norm = m.params()
+    return params, norm, float(losses[-1])
+
+
+def _run_batch(seeds, mode, model=None):
+    b = pa.Batch(_runs(seeds), dict(beta_f=BF, alpha_star=ALPHA, alpha_tol=0.01, theta=THETA, mode=mode))
+    if model is not None:
+        b.set_model(*model)
+    t0 = time.perf_counter()
+    b.run()
+    return b, time.perf_counter() - t0
+
+
+def test_learned_runs_accept_proposals_and_match_accuracy(trained):
+    params, norm, loss = trained
+    seeds = range(101, 117)
+    ba, ta = _run_batch(seeds, "adaptive")
+    bl, tl = _run_batch(seeds, "learned", (params, norm))
+    props = acc = 0
+    err_a, err_l = [], []
+    for r, spec in enumerate(_runs(seeds)):
+        assert ba.status(r) == pa.PA_OK and bl.status(r) == pa.PA_OK
+        assert bl.state(r)["beta"] == BF
+        p, a = bl.learned_stats(r)
+        props += p
+        acc += a
+        ex = exact.torus_exact(spec["L"], BF)["betaF_per_N"]
+        err_a.append(ba.history(r)[-1]["betaF_per_N"] - ex)
+        err_l.append(bl.history(r)[-1]["betaF_per_N"] - ex)
+        # every step of the learned schedule keeps enough overlap: R_i stays near R
+        for o in bl.history(r)[1:]:
+            assert abs(o["R"] - spec["R"]) < 5 * np.sqrt(spec["R"])
+    rate = acc / max(props, 1)
+    print("learned: %d proposals, %d accepted (%.2f); adaptive %.3f s, learned %.3f s; "
+          "|dF| adaptive %.2e learned %.2e; final training loss %.3f"
+          % (props, acc, rate, ta, tl, np.mean(np.abs(err_a)), np.mean(np.abs(err_l)), loss), flush=True)
+    assert props > 0 and rate > 0.5
+    # equal free-energy accuracy within the statistical spread of the runs
+    sd = np.std(err_a) / np.sqrt(len(err_a)) + np.std(err_l) / np.sqrt(len(err_l))
+    assert abs(np.mean(err_l)) < abs(np.mean(err_a)) + 4 * sd + 1e-4
+
+
+def test_features_are_the_population_moments(trained):
+    params, norm, _ = trained
+    b = pa.Batch(_runs([7]), dict(beta_f=0.4, alpha_star=ALPHA, alpha_tol=0.01, theta=THETA, mode="learned"))
+    b.set_model(params, norm)
+    for _ in range(3):
+        b.step()
+    x, valid, prop = b.features(0)
+    _, E, _ = b.download_population(0)
+    st = b.state(0)
+    hist = b.history(0)
+    E = E.astype(np.float64)
+    mu, sd = E.mean(), E.std()
+    assert valid
+    assert x[0] == pytest.approx(mu / 256, rel=1e-6)
+    assert x[1] == pytest.approx(np.log(sd), rel=1e-6)
+    assert x[2] == pytest.approx(((E - mu) ** 3).mean() / sd ** 3, rel=1e-4, abs=1e-5)
+    assert x[3] == pytest.approx(((E - mu) ** 4).mean() / sd ** 4 - 3, rel=1e-4, abs=1e-5)
+    assert x[4] == pytest.approx(st["beta"], rel=1e-7)
+    assert x[5] == pytest.approx(np.log(16.0)) and x[6] == pytest.approx(np.log(1000.0))
+    assert x[7] == pytest.approx(np.log(hist[-1]["beta"] - hist[-2]["beta"]), rel=1e-6)
+    assert np.isfinite(prop)

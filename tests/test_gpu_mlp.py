@@ -1,0 +1,92 @@
+"""The learned proposer's GPU kernels against the FP64 reference MLP
+(oracle/mlp.py): gradients, FP32 and BF16 inference, normalisation, and
+deterministic training that reduces the loss."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+pa = pytest.importorskip("paper_1703_03676_amd")
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _data(seed, n):
+    rng = np.random.default_rng(seed)
+    params = rng.normal(0, 0.25, mlp.NPARAMS).astype(np.float32)
+    norm = np.concatenate([rng.normal(0, 1, 8), rng.uniform(0.5, 2, 8), [-5.0, 1.5]]).astype(np.float32)
+    x = (rng.normal(0, 1, (n, 8)) * norm[8:16] + norm[:8]).astype(np.float32)
+    t = (rng.normal(-5.0, 1.5, n)).astype(np.float32)
+    return params, norm, x, t
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def test_gradient_matches_fp64_reference():
+    print("case mlp gradient", flush=True)
+    params, norm, x, t = _data(0, 300)
+    m = pa.Mlp(max_batch=512, seed=1)
+    m.set_params(params, norm)
+    g, loss = m.gradient(_cuda(x), _cuda(t))
+    gr = mlp.gradient(params.astype(np.float64), norm.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    lr = mlp.loss(params.astype(np.float64), norm.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    scale = np.abs(gr).max()
+    assert np.all(np.abs(g - gr) <= 1e-4 * scale + 1e-4 * np.abs(gr))
+    assert loss == pytest.approx(lr, rel=1e-5)
+
+
+def test_inference_fp32_and_bf16():
+    print("case mlp inference", flush=True)
+    params, norm, x, _ = _data(2, 200)
+    m = pa.Mlp(max_batch=64, seed=1)
+    m.set_params(params, norm)
+    ref = mlp.predict(params.astype(np.float64), norm.astype(np.float64), x.astype(np.float64))
+    y32 = m.forward(_cuda(x), bf16=False).cpu().numpy()
+    y16 = m.forward(_cuda(x), bf16=True).cpu().numpy()
+    tsd = float(norm[17])
+    assert np.all(np.abs(y32 - ref) <= 1e-5 * (np.abs(ref) + tsd))
+    # BF16 weights and activations (8-bit mantissa), FP32 accumulation
+    err = np.abs(y16 - ref) / tsd
+    assert err.max() < 0.1 and np.median(err) < 0.02
+
+
+def test_fit_norm():
+    _, _, x, t = _data(3, 5000)
+    m = pa.Mlp(max_batch=64, seed=1)
+    m.fit_norm(_cuda(x), _cuda(t))
+    _, norm = m.params()
+    assert np.allclose(norm[:8], x.astype(np.float64).mean(axis=0), rtol=1e-5, atol=1e-5)
+    assert np.allclose(norm[8:16], x.astype(np.float64).std(axis=0), rtol=1e-4)
+    assert norm[16] == pytest.approx(t.astype(np.float64).mean(), rel=1e-5)
+    assert norm[17] == pytest.approx(t.astype(np.float64).std(), rel=1e-4)
+
+
+def test_training_is_deterministic_and_learns():
+    print("case mlp training", flush=True)
+    rng = np.random.default_rng(4)
+    n = 4096
+    x = rng.normal(0, 1, (n, 8)).astype(np.float32)
+    t = (-4.0 - 0.8 * x[:, 1] + 0.3 * x[:, 2] * x[:, 3] + 0.2 * np.tanh(x[:, 4])).astype(np.float32)
+    out = []
+    for rep in range(2):
+        m = pa.Mlp(max_batch=256, seed=7)
+        m.fit_norm(_cuda(x), _cuda(t))
+        losses = m.train(_cuda(x), _cuda(t), batch=128, epochs=25, lr=5e-3, momentum=0.9, seed=11)
+        out.append((m.params()[0], losses))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+    losses = out[0][1]
+    assert losses[-1] < 0.05 and losses[-1] < 0.2 * losses[0]  # normalised MSE (target variance 1)
+    # the trained network against the FP64 reference on its own weights
+    p, norm = out[0][0], m.params()[1]
+    pred = mlp.predict(p.astype(np.float64), norm.astype(np.float64), x[:256].astype(np.float64))
+    assert np.mean((pred - t[:256]) ** 2) < 0.05 * np.var(t)
