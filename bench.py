@@ -136,6 +136,158 @@ def cpu_baseline(seconds_target=15.0):
     }
 
 
+def _exact_betaF(L, beta):
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import exact  # exact finite-torus solution, used only to report accuracy
+    return exact.torus_exact(L, beta)["betaF_per_N"]
+
+
+def run_plain_adaptive(pa, L, R_, theta, alpha, beta_f, seed, mhr=False):
+    """One run through the single-run C ABI with host bisection each step."""
+    run = pa.Run(L, R_, seed=seed, layout="bits", mhr=mhr)
+    run.observables()
+    flips = 0
+    nsteps = 0
+    while run.state()["beta"] < beta_f:
+        b = run.adapt_beta(alpha, beta_f)
+        run.resample(b)
+        flips += L * L * theta * run.state()["R"]
+        run.sweep(theta)
+        run.observables()
+        nsteps += 1
+    return run, flips, nsteps
+
+
+def workload_config3(pa, torch):
+    """L=128, R=50000, theta=50, adaptive dbeta (alpha*=0.85), multi-histogram
+    reweighting on a 1000-point beta grid; plain single-run form."""
+    import numpy as np
+    L, R_, theta = 128, 50000, 50
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run, flips, nsteps = run_plain_adaptive(pa, L, R_, theta, 0.85, 1.0, seed=1, mhr=True)
+    torch.cuda.synchronize()
+    t_run = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    rw = run.reweight(np.linspace(0.0, 1.0, 1000))
+    t_rw = time.perf_counter() - t1
+    last = run.observables()
+    return {
+        "workload": "config3: L=128, R=50000, theta=50, adaptive alpha*=0.85, beta 0->1, MHR on 1000 betas",
+        "flips_per_ns": flips / (t_run * 1e9), "run_wall_time_s": t_run, "temperature_steps": nsteps,
+        "reweight_s": t_rw, "betaF_per_N_final": last["betaF_per_N"],
+        "betaF_per_N_exact": _exact_betaF(L, 1.0),
+        "mhr_C_peak_beta": float(np.linspace(0.0, 1.0, 1000)[int(np.argmax([o["C"] for o in rw]))]),
+    }
+
+
+CONFIG4_LR = [(L, R_) for L in (16, 32, 64, 128) for R_ in (5000, 20000)]
+
+
+def _config4_runs(seed0):
+    return [dict(L=L, R=R_, seed=seed0 + 8 * k + s, layout="bits")
+            for k, (L, R_) in enumerate(CONFIG4_LR) for s in range(8)]
+
+
+def _batch_errors(b, runs):
+    return [abs(b.history(r)[-1]["betaF_per_N"] - _exact_betaF(sp["L"], 1.0)) for r, sp in enumerate(runs)]
+
+
+def workload_config4(pa, torch, sequential=True):
+    """64 runs, (L, R) in {16,32,64,128} x {5000,20000}, theta=20, adaptive
+    alpha*=0.85, beta 0->1: plain adaptive one run at a time, batched
+    adaptive (one graph replay per step for all runs) and batched learned."""
+    import numpy as np
+    theta, alpha = 20, 0.85
+    out = {"workload": "config4: 64 runs, (L,R) in {16,32,64,128}x{5000,20000}, 8 seeds each, theta=20, "
+                       "adaptive alpha*=0.85, beta 0->1"}
+    runs = _config4_runs(1)
+    if sequential:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        errs, flips, steps = [], 0, 0
+        for sp in runs:
+            run, f, n = run_plain_adaptive(pa, sp["L"], sp["R"], theta, alpha, 1.0, sp["seed"])
+            errs.append(abs(run.observables()["betaF_per_N"] - _exact_betaF(sp["L"], 1.0)))
+            flips += f
+            steps += n
+            run.close()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out["plain_adaptive"] = {"s_per_run": t / len(runs), "total_s": t, "flips_per_ns": flips / (t * 1e9),
+                                 "steps": steps, "mean_abs_dbetaF_per_N": float(np.mean(errs))}
+    sched = dict(beta_f=1.0, alpha_star=alpha, alpha_tol=0.01, theta=theta, mode="adaptive")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = pa.Batch(runs, sched)
+    b.run()
+    t = time.perf_counter() - t0
+    steps = sum(len(b.history(r)) - 1 for r in range(len(runs)))
+    flips = sum(sp["L"] ** 2 * theta * o["R"] for r, sp in enumerate(runs) for o in b.history(r)[1:])
+    out["batched_adaptive"] = {"s_per_run": t / len(runs), "total_s": t, "flips_per_ns": flips / (t * 1e9),
+                               "steps": steps, "mean_abs_dbetaF_per_N": float(np.mean(_batch_errors(b, runs)))}
+    # learned: train on the bisection pairs of the adaptive batch, then new seeds
+    x, tt = b.training_pairs()
+    b.close()
+    m = pa.Mlp(max_batch=512, seed=0)
+    xc, tc = torch.from_numpy(x).cuda(), torch.from_numpy(tt).cuda()
+    t0 = time.perf_counter()
+    m.fit_norm(xc, tc)
+    losses = m.train(xc, tc, batch=256, epochs=200, lr=3e-3, momentum=0.9, seed=1)
+    t_train = time.perf_counter() - t0
+    params, norm = m.params()
+    runs2 = _config4_runs(1001)
+    sched2 = dict(sched, mode="learned")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bl = pa.Batch(runs2, sched2)
+    bl.set_model(params, norm)
+    bl.run()
+    t = time.perf_counter() - t0
+    props = sum(bl.learned_stats(r)[0] for r in range(len(runs2)))
+    acc = sum(bl.learned_stats(r)[1] for r in range(len(runs2)))
+    steps = sum(len(bl.history(r)) - 1 for r in range(len(runs2)))
+    flips = sum(sp["L"] ** 2 * theta * o["R"] for r, sp in enumerate(runs2) for o in bl.history(r)[1:])
+    out["batched_learned"] = {"s_per_run": t / len(runs2), "total_s": t, "flips_per_ns": flips / (t * 1e9),
+                              "steps": steps, "proposals": props, "accepted": acc,
+                              "mean_abs_dbetaF_per_N": float(np.mean(_batch_errors(bl, runs2))),
+                              "training_pairs": int(len(tt)), "train_s": t_train,
+                              "train_loss_first_last": [float(losses[0]), float(losses[-1])]}
+    out["_model"] = (params, norm)
+    return out
+
+
+def workload_config5(pa, torch):
+    """L=256, R=100000, theta=20, beta 0->1: plain adaptive single run, then a
+    batched learned run with a proposer trained on config-4 adaptive pairs."""
+    c4 = workload_config4(pa, torch, sequential=False)
+    params, norm = c4.pop("_model")
+    L, R_, theta = 256, 100000, 20
+    out = {"workload": "config5: L=256, R=100000, theta=20, beta 0->1, adaptive vs learned (alpha*=0.85)"}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run, flips, nsteps = run_plain_adaptive(pa, L, R_, theta, 0.85, 1.0, seed=5)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out["plain_adaptive"] = {"run_wall_time_s": t, "flips_per_ns": flips / (t * 1e9), "steps": nsteps,
+                             "betaF_per_N_error": abs(run.observables()["betaF_per_N"] - _exact_betaF(L, 1.0))}
+    run.close()
+    b = pa.Batch([dict(L=L, R=R_, seed=6, layout="bits")],
+                 dict(beta_f=1.0, alpha_star=0.85, alpha_tol=0.01, theta=theta, mode="learned"))
+    b.set_model(params, norm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run()
+    t = time.perf_counter() - t0
+    h = b.history(0)
+    flips = sum(L * L * theta * o["R"] for o in h[1:])
+    p, a = b.learned_stats(0)
+    out["batched_learned"] = {"run_wall_time_s": t, "flips_per_ns": flips / (t * 1e9), "steps": len(h) - 1,
+                              "proposals": p, "accepted": a,
+                              "betaF_per_N_error": abs(h[-1]["betaF_per_N"] - _exact_betaF(L, 1.0))}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +295,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--layouts", default="bits,int8")
+    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5"],
+                    help="config2 (default) is the headline workload; the others print their own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -156,6 +310,12 @@ def main():
         from paper_1703_03676_amd import build as hip_build
         hip_build.build()
     torch.cuda.set_device(0)
+    if args.workload != "config2":
+        fn = {"config3": workload_config3, "config4": workload_config4, "config5": workload_config5}[args.workload]
+        res = fn(pa, torch)
+        res.pop("_model", None)
+        print(json.dumps(res), flush=True)
+        return 0
     layouts = args.layouts.split(",")
     res = {lay: time_layout(pa, torch, lay, args.steps, args.warmup) for lay in layouts}
     head = res[layouts[0]]
