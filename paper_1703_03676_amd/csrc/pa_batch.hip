@@ -225,7 +225,6 @@ template <int L, bool INT8>
 __global__ __launch_bounds__(512) void b_sweep(const Item* __restrict__ items, const RunDev* __restrict__ runs,
                                                const StepDev* __restrict__ steps, const ResultDev* __restrict__ res)
 {
-    using Gm = Geo<L>;
     extern __shared__ uint32_t lds_dyn[];
     const Item it = items[blockIdx.x];
     const StepDev st = steps[it.run];
@@ -248,21 +247,7 @@ __global__ __launch_bounds__(512) void b_sweep(const Item* __restrict__ items, c
     a.t4l = st.t4l;
     a.init = st.init;
     const int wpb = (int)(blockDim.x >> 6);
-    if (it.blk * wpb * Gm::REPW >= n) return;  // uniform per block
-    LaneInfo li;
-    li.lane = (int)(threadIdx.x & 63u);
-    li.gl = li.lane % Gm::G;
-    const int wave = it.blk * wpb + (int)(threadIdx.x >> 6);
-    int jj = wave * Gm::REPW + li.lane / Gm::G;
-    if constexpr (Gm::REPW == 1) jj = __builtin_amdgcn_readfirstlane(jj);
-    li.j = (uint32_t)jj;
-    li.valid = jj < n;
-    if constexpr (Gm::K == 1) {
-        if (wave * Gm::REPW >= n) return;  // uniform per wave; no barriers on this path
-        sweep_regs<L, INT8>(a, li);
-    } else {
-        sweep_lds<L, INT8>(a, li, lds_dyn + (threadIdx.x >> 6) * 2 * Gm::NW);
-    }
+    sweep_waves<L, INT8>(a, it.blk * wpb, wpb, lds_dyn);
 }
 
 __global__ __launch_bounds__(kBlock) void b_stats_reset(const RunDev* __restrict__ runs,
@@ -679,7 +664,7 @@ hipError_t launch_group_t(const Item* items, size_t n, int wpb, const RunDev* rd
                           const ResultDev* rs, hipStream_t s)
 {
     using Gm = pa::dev::Geo<L>;
-    const size_t lds = (Gm::K == 1) ? 0 : (size_t)wpb * 2 * Gm::NW * 4;
+    const size_t lds = (size_t)Gm::lds_words(wpb) * 4;
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL((b_sweep<L, INT8>), dim3((unsigned)n), dim3(64 * wpb), lds, s, items, rd, st, rs);
     return hipGetLastError();
@@ -701,9 +686,25 @@ hipError_t launch_group(int L, int layout, const Item* items, size_t n, int wpb,
 
 int reps_per_wave(int L)
 {
-    const int NW = L * L / 64;
-    const int G = NW < 64 ? NW : 64;
-    return 64 / G;
+    switch (L) {
+    case 16: return pa::dev::Geo<16>::RPWV;
+    case 32: return pa::dev::Geo<32>::RPWV;
+    case 64: return pa::dev::Geo<64>::RPWV;
+    case 128: return pa::dev::Geo<128>::RPWV;
+    default: return pa::dev::Geo<256>::RPWV;
+    }
+}
+
+// LDS bytes of a sweep block of wpb waves.
+size_t sweep_lds_bytes(int L, int wpb)
+{
+    switch (L) {
+    case 16: return (size_t)pa::dev::Geo<16>::lds_words(wpb) * 4;
+    case 32: return (size_t)pa::dev::Geo<32>::lds_words(wpb) * 4;
+    case 64: return (size_t)pa::dev::Geo<64>::lds_words(wpb) * 4;
+    case 128: return (size_t)pa::dev::Geo<128>::lds_words(wpb) * 4;
+    default: return (size_t)pa::dev::Geo<256>::lds_words(wpb) * 4;
+    }
 }
 
 // Sweep items of one group for a given number of waves per block.
@@ -1291,7 +1292,7 @@ pa_status autotune(pa_batch* b)
         float best = 1e30f;
         int best_w = 1;
         for (int wpb : cands) {
-            if (g.L >= 128 && wpb > 4) continue;  // LDS path: at most 4 replicas (32 KB) per block
+            if (sweep_lds_bytes(g.L, wpb) > 65536) continue;  // at most 64 KB of LDS per block
             it = sweep_items(b, g.L, g.layout, wpb);
             const size_t off = g.item_off;  // scratch slot: the group's own item range is large enough
             BCHK(hipMemcpyAsync(b->d_items + off, it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice,

@@ -68,6 +68,14 @@ struct Geo {
     static constexpr int RL = WIDE ? K / WPR : 1;     // rows per lane (wide)
     static constexpr int RPW = WIDE ? 1 : 32 / HW;    // rows per word (narrow)
     static constexpr size_t BITS_BYTES = N / 8;       // bytes per replica, bit store
+    static constexpr int RPWV = (K == 1) ? REPW : 1;  // replicas per wave
+    // LDS path: a lane decides up to 8 of its K words before the sites still
+    // tied are resolved through the wave's tie queue (QCAP entries).
+    static constexpr int SLOTS = (K == 1) ? 1 : (K < 8 ? K : 8);
+    static constexpr int QCAP = 256;
+    // LDS words of one wave on the LDS path: replica [2][NW], queue, slot results
+    static constexpr int WAVE_LDS_WORDS = (K == 1) ? 0 : 2 * NW + QCAP + SLOTS * 64;
+    static constexpr int lds_words(int wpb) { return wpb * WAVE_LDS_WORDS; }
     static_assert(L % 16 == 0 && L >= 16 && L <= 256, "lattice size");
     static_assert(K >= 1 && NW % G == 0, "lane mapping");
 };
@@ -253,6 +261,162 @@ __device__ __forceinline__ void half_sweep(uint32_t (&own)[Geo<L>::K], const uin
     }
 }
 
+
+// Decisions of the first 8 bit planes (Philox blocks 0 and 1) for the 32
+// sites of a word.  A site flips if at least two of its four neighbours are
+// anti-aligned (k = s h <= 0); a site with one anti-aligned neighbour (k = 2,
+// `cls1`) or none (k = 4) flips if its uniform x is below T_2 or T_4.  The
+// high 8 bits of x are compared with those of T as an 8-bit subtraction, least
+// significant plane first: the borrow b' = maj(~x, b, t) of the last plane is
+// "x < T", and e tracks equality.  The threshold bits are uniform masks (0 or
+// ~0), so every plane is four branch-free bit operations for both classes.
+// Returns the sites accepted; `tie` receives the sites whose 8 high bits equal
+// the threshold's (probability 2^-8 each), decided later by decide_tail.
+__device__ __forceinline__ uint32_t decide8(uint32_t w, const Nb& n, uint32_t v, uint32_t ctr1, uint32_t j,
+                                            const SweepArgs& a, uint32_t& tie, uint32_t& cls1)
+{
+    const uint32_t d1 = w ^ n.up, d2 = w ^ n.dn, d3 = w ^ n.same, d4 = w ^ n.side;
+    const uint32_t o12 = d1 | d2, a12 = d1 & d2, o34 = d3 | d4, a34 = d3 & d4;
+    const uint32_t ge2 = a12 | a34 | (o12 & o34);
+    const uint32_t any = o12 | o34;
+    cls1 = any & ~ge2;                                     // k = 2
+    const uint32_t cls2 = ~any;                            // k = 4
+    const uint32_t all2 = (a.t2h > 0xFFFFu) ? cls1 : 0u;   // T = 2^32: always accepted
+    const uint32_t all4 = (a.t4h > 0xFFFFu) ? cls2 : 0u;
+    const uint32_t u2 = cls1 & ~all2, u4 = cls2 & ~all4;   // sites that need their uniform
+    uint32_t acc = ge2 | all2 | all4;
+    tie = 0u;
+    if (!__any((u2 | u4) != 0u)) return acc;
+    const U4 P0 = philox10(4u * v, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+    const U4 P1 = philox10(4u * v + 1u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+    const uint32_t pl[8] = {P0.x, P0.y, P0.z, P0.w, P1.x, P1.y, P1.z, P1.w};
+    uint32_t b2 = 0u, b4 = 0u, e2 = ~0u, e4 = ~0u;
+#pragma unroll
+    for (int p = 7; p >= 0; --p) {
+        const uint32_t m2 = 0u - ((a.t2h >> (15 - p)) & 1u);
+        const uint32_t m4 = 0u - ((a.t4h >> (15 - p)) & 1u);
+        b2 = __builtin_amdgcn_bitop3_b32(pl[p], b2, m2, 0x8E);  // maj(~x, b, t)
+        b4 = __builtin_amdgcn_bitop3_b32(pl[p], b4, m4, 0x8E);
+        e2 = __builtin_amdgcn_bitop3_b32(e2, pl[p], m2, 0x90);  // e & ~(x ^ t)
+        e4 = __builtin_amdgcn_bitop3_b32(e4, pl[p], m4, 0x90);
+    }
+    acc |= (u2 & b2) | (u4 & b4);
+    tie = (u2 & e2) | (u4 & e4);
+    return acc;
+}
+
+// Remaining comparison of site b of word v, tied after 8 planes: planes 8..15
+// (Philox blocks 2 and 3, four planes each, compared as nibbles), then the low
+// 16 bits from the SWEEP-LOW stream.  True if the site flips.
+__device__ __forceinline__ bool decide_tail(uint32_t v, uint32_t b, bool k2, uint32_t ctr1, uint32_t j,
+                                            const SweepArgs& a)
+{
+    const uint32_t th = k2 ? a.t2h : a.t4h;
+#pragma unroll
+    for (int kk = 2; kk < 4; ++kk) {
+        const U4 P = philox10(4u * v + (uint32_t)kk, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+        const uint32_t x = (((P.x >> b) & 1u) << 3) | (((P.y >> b) & 1u) << 2) | (((P.z >> b) & 1u) << 1) |
+                           ((P.w >> b) & 1u);
+        const uint32_t t = (th >> (12 - 4 * kk)) & 15u;
+        if (x != t) return x < t;
+    }
+    const uint32_t q = 32u * v + b;
+    const U4 P = philox10(q >> 3, ctr1, j, kStreamSweepLow, a.key0, a.key1);
+    const uint32_t word = pick(P, (q >> 1) & 3u);
+    const uint32_t lo = (q & 1u) ? (word & 0xFFFFu) : (word >> 16);
+    return lo < (k2 ? a.t2l : a.t4l);
+}
+
+// Exclusive prefix sum over the 64 lanes of the wave; *total gets the sum.
+__device__ __forceinline__ uint32_t wave_prefix(uint32_t x, int lane, uint32_t* total)
+{
+    uint32_t incl = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = (uint32_t)__shfl_up((int)incl, off);
+        if (lane >= off) incl += y;
+    }
+    *total = (uint32_t)__shfl((int)incl, 63);
+    return incl - x;
+}
+
+// Orders the LDS accesses of one wave: everything before is complete and
+// visible to every lane of the wave after.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Tie queue of one wave.  The sites still tied after decide8 are rare (2^-8
+// each), so instead of evaluating the later Philox blocks for every word, the
+// tied sites of the S words of every lane are queued in LDS and decided one per
+// lane.  An entry is  bits 0-4 site | bit 5 class k = 2 | bits 6-11 lane |
+// bits 12-15 slot  (slot: which of the lane's S words); the decisions are
+// ORed into res[slot * 64 + lane].
+__device__ __forceinline__ uint32_t tie_entry(int s, int lane, uint32_t k2bit, uint32_t b)
+{
+    return ((uint32_t)s << 12) | ((uint32_t)lane << 6) | (k2bit << 5) | b;
+}
+
+// Tie resolution of the wave: queue[QCAP], res[S * 64] (zero on entry and on
+// return).  vj(lane, slot, &v, &j) gives the word and replica of a lane's
+// slot; extra[s] receives the additional flips of the lane's word s.  If the
+// queue would overflow, every lane decides its own tied sites instead.
+template <int S, int QCAP, class VJ>
+__device__ __forceinline__ void resolve_ties_wave(const uint32_t (&tie)[S], const uint32_t (&cls1)[S], int lane,
+                                                  uint32_t ctr1, const SweepArgs& a, uint32_t* queue, uint32_t* res,
+                                                  uint32_t (&extra)[S], const VJ& vj)
+{
+#pragma unroll
+    for (int s = 0; s < S; ++s) extra[s] = 0u;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) cnt += __popc(tie[s]);
+    uint32_t total;
+    uint32_t off = wave_prefix(cnt, lane, &total);
+    if (total == 0u) return;
+    if (total > (uint32_t)QCAP) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            uint32_t t = tie[s];
+            uint32_t v, j;
+            vj(lane, s, &v, &j);
+            while (t) {
+                const uint32_t b = (uint32_t)__builtin_ctz(t);
+                t &= t - 1u;
+                if (decide_tail(v, b, (cls1[s] >> b) & 1u, ctr1, j, a)) extra[s] |= 1u << b;
+            }
+        }
+        return;
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        uint32_t t = tie[s];
+        while (t) {
+            const uint32_t b = (uint32_t)__builtin_ctz(t);
+            t &= t - 1u;
+            queue[off++] = tie_entry(s, lane, (cls1[s] >> b) & 1u, b);
+        }
+    }
+    wave_lds_sync();
+    for (uint32_t i = (uint32_t)lane; i < total; i += 64u) {
+        const uint32_t e = queue[i];
+        const int s = (int)((e >> 12) & 15u), owner = (int)((e >> 6) & 63u);
+        const uint32_t b = e & 31u;
+        uint32_t v, j;
+        vj(owner, s, &v, &j);
+        if (decide_tail(v, b, (e >> 5) & 1u, ctr1, j, a)) atomicOr(&res[s * 64 + owner], 1u << b);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        extra[s] = res[s * 64 + lane];
+        res[s * 64 + lane] = 0u;
+    }
+}
+
 // Sign bits of 64 consecutive int8 spins -> (even-x bits, odd-x bits).
 __device__ __forceinline__ void pack64(const uint4* src, uint32_t& ev, uint32_t& od)
 {
@@ -398,9 +562,10 @@ __device__ __forceinline__ void sweep_regs(const SweepArgs& a, const LaneInfo& l
     if (li.valid) store_word<L, INT8>(a, li.j, v, s0[0], s1[0]);
 }
 
-// LDS-resident sweep for rows of whole words (L >= 128): one wave per block
-// owns one replica; word (k, lane) of a colour sits at k * 64 + lane, so the
-// 64 lanes touch 64 consecutive words for every k.
+
+// LDS-resident sweep for rows of whole words (L >= 128): one wave owns one
+// replica; word (k, lane) of a colour sits at k * 64 + lane, so the 64 lanes
+// touch 64 consecutive words for every k.
 template <int L>
 struct LdsRep {
     using Gm = Geo<L>;
@@ -428,47 +593,67 @@ struct LdsRep {
     }
 };
 
-template <int L, bool INT8, int C>
-__device__ __forceinline__ void half_sweep_lds(const LdsRep<L>& rep, int gl, uint32_t g, uint32_t j, const SweepArgs& a)
+// One colour of a sweep on the LDS path: the lane's K words in chunks of
+// SLOTS, each chunk followed by the wave's tie resolution.
+template <int L, int C>
+__device__ __forceinline__ void half_sweep_lds(const LdsRep<L>& rep, int gl, uint32_t g, uint32_t j,
+                                               const SweepArgs& a, uint32_t* queue, uint32_t* res)
 {
+    using Gm = Geo<L>;
+    constexpr int S = Gm::SLOTS;
+    static_assert(Gm::K % S == 0, "slots divide the words of a lane");
     const uint32_t ctr1 = 2u * g + (uint32_t)C;
 #pragma unroll 1
-    for (int k = 0; k < Geo<L>::K; ++k) {
-        const uint32_t v = (uint32_t)(gl * Geo<L>::K + k);
-        const Nb n = rep.template nb<C>(k, gl);
-        uint32_t& own = rep.at(C, k, gl);
-        own ^= accept_mask(own, n, v, ctr1, j, a);
+    for (int k0 = 0; k0 < Gm::K; k0 += S) {
+        uint32_t tie[S], k2[S], extra[S];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int k = k0 + s;
+            const Nb n = rep.template nb<C>(k, gl);
+            uint32_t& own = rep.at(C, k, gl);
+            own ^= decide8(own, n, (uint32_t)(gl * Gm::K + k), ctr1, j, a, tie[s], k2[s]);
+        }
+        const auto vj = [&](int owner, int s, uint32_t* vo, uint32_t* jo) {
+            *vo = (uint32_t)(owner * Gm::K + k0 + s);
+            *jo = j;
+        };
+        resolve_ties_wave<S, Gm::QCAP>(tie, k2, gl, ctr1, a, queue, res, extra, vj);
+#pragma unroll
+        for (int s = 0; s < S; ++s) rep.at(C, k0 + s, gl) ^= extra[s];
     }
-    __syncthreads();
+    wave_lds_sync();
 }
 
-// All waves of a block take part in every barrier: a wave whose replica is
-// beyond the population (valid == false) runs on zero words and stores nothing.
+// The wave's LDS: replica [2][NW], then the tie queue and the slot results.
 template <int L, bool INT8>
-__device__ __forceinline__ void sweep_lds(const SweepArgs& a, const LaneInfo& li, uint32_t* lds)
+__device__ __forceinline__ void sweep_lds(const SweepArgs& a, uint32_t j, uint32_t* lds)
 {
     using Gm = Geo<L>;
     static_assert(Gm::WIDE && Gm::RL % 2 == 0 && Gm::G == 64, "LDS path layout");
     const LdsRep<L> rep{lds};
-    const int gl = li.gl;
+    uint32_t* queue = lds + 2 * Gm::NW;
+    uint32_t* res = queue + Gm::QCAP;
+    const int gl = (int)(threadIdx.x & 63u);
+#pragma unroll
+    for (int s = 0; s < Gm::SLOTS; ++s) res[s * 64 + gl] = 0u;
 #pragma unroll 1
     for (int k = 0; k < Gm::K; ++k) {
         const uint32_t v = (uint32_t)(gl * Gm::K + k);
-        uint32_t w0 = 0, w1 = 0;
+        uint32_t w0, w1;
         if (a.init) {
-            w0 = init_word<L>(0, v, li.j, a);
-            w1 = init_word<L>(1, v, li.j, a);
-        } else if (li.valid) {
-            load_word<L, INT8>(a, li.j, v, w0, w1);
+            w0 = init_word<L>(0, v, j, a);
+            w1 = init_word<L>(1, v, j, a);
+        } else {
+            load_word<L, INT8>(a, j, v, w0, w1);
         }
         rep.at(0, k, gl) = w0;
         rep.at(1, k, gl) = w1;
     }
-    __syncthreads();
+    wave_lds_sync();
     for (int t = 0; t < a.nsweeps; ++t) {
         const uint32_t g = a.g0 + (uint32_t)t;
-        half_sweep_lds<L, INT8, 0>(rep, gl, g, li.j, a);
-        half_sweep_lds<L, INT8, 1>(rep, gl, g, li.j, a);
+        half_sweep_lds<L, 0>(rep, gl, g, j, a, queue, res);
+        half_sweep_lds<L, 1>(rep, gl, g, j, a, queue, res);
     }
     uint32_t anti = 0, downs = 0;
 #pragma unroll 1
@@ -477,15 +662,46 @@ __device__ __forceinline__ void sweep_lds(const SweepArgs& a, const LaneInfo& li
         const uint32_t w0 = rep.at(0, k, gl), w1 = rep.at(1, k, gl);
         anti += __popc(w0 ^ n.up) + __popc(w0 ^ n.dn) + __popc(w0 ^ n.same) + __popc(w0 ^ n.side);
         downs += __popc(w0) + __popc(w1);
-        if (li.valid) store_word<L, INT8>(a, li.j, (uint32_t)(gl * Gm::K + k), w0, w1);
+        store_word<L, INT8>(a, j, (uint32_t)(gl * Gm::K + k), w0, w1);
     }
+    LaneInfo li;
+    li.lane = gl;
+    li.gl = gl;
+    li.j = j;
+    li.valid = true;
     write_EM<L>(a, li, anti, downs);
 }
 
+// Threads per block of the single-run sweep kernel.
 template <int L>
 constexpr int sweep_block()
 {
     return Geo<L>::K == 1 ? kBlock : 64;
+}
+
+// Sweep entry shared by the single-run and batched kernels, for the block
+// holding waves [wave0, wave0 + wpb) of a run (wpb = blockDim.x / 64); lds is
+// the block's Geo<L>::lds_words(wpb) words (none on the register path).
+// Waves share no barrier: each returns as soon as it holds no replica.
+template <int L, bool INT8>
+__device__ __forceinline__ void sweep_waves(const SweepArgs& a, int wave0, int wpb, uint32_t* lds)
+{
+    using Gm = Geo<L>;
+    const int lane = (int)(threadIdx.x & 63u), wib = (int)(threadIdx.x >> 6);
+    const int wave = wave0 + wib;
+    if (wave * Gm::RPWV >= a.n_rep) return;  // uniform per wave
+    if constexpr (Gm::K == 1) {
+        LaneInfo li;
+        li.lane = lane;
+        li.gl = lane % Gm::G;
+        int jj = wave * Gm::REPW + lane / Gm::G;
+        if constexpr (Gm::REPW == 1) jj = __builtin_amdgcn_readfirstlane(jj);
+        li.j = (uint32_t)jj;
+        li.valid = jj < a.n_rep;
+        sweep_regs<L, INT8>(a, li);
+    } else {
+        sweep_lds<L, INT8>(a, (uint32_t)__builtin_amdgcn_readfirstlane(wave), lds + wib * Gm::WAVE_LDS_WORDS);
+    }
 }
 
 __device__ __forceinline__ void add_u128(uint64_t& lo, uint64_t& hi, uint64_t blo, uint64_t bhi)

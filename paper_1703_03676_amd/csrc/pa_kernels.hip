@@ -28,21 +28,9 @@ template <int L, bool INT8>
 __global__ __launch_bounds__(sweep_block<L>()) void sweep_kernel(SweepArgs a)
 {
     using Gm = Geo<L>;
-    LaneInfo li;
-    li.lane = (int)(threadIdx.x & 63u);
-    li.gl = li.lane % Gm::G;
-    const int wave = (int)((blockIdx.x * sweep_block<L>() + threadIdx.x) >> 6);
-    if (wave * Gm::REPW >= a.n_rep) return;  // uniform per wave (per block on the LDS path)
-    int jj = wave * Gm::REPW + li.lane / Gm::G;
-    if constexpr (Gm::REPW == 1) jj = __builtin_amdgcn_readfirstlane(jj);
-    li.j = (uint32_t)jj;
-    li.valid = jj < a.n_rep;
-    if constexpr (Gm::K == 1) {
-        sweep_regs<L, INT8>(a, li);
-    } else {
-        __shared__ uint32_t lds[2 * Gm::NW];
-        sweep_lds<L, INT8>(a, li, lds);
-    }
+    constexpr int WPB = sweep_block<L>() / 64;
+    __shared__ uint32_t lds[Gm::lds_words(WPB) > 0 ? Gm::lds_words(WPB) : 1];
+    sweep_waves<L, INT8>(a, (int)blockIdx.x * WPB, WPB, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -203,7 +191,7 @@ template <int L, bool INT8>
 hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t s)
 {
     using Gm = Geo<L>;
-    const int reps_per_block = (sweep_block<L>() / 64) * Gm::REPW;
+    const int reps_per_block = (sweep_block<L>() / 64) * Gm::RPWV;
     const int blocks = (a.n_rep + reps_per_block - 1) / reps_per_block;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL((sweep_kernel<L, INT8>), dim3(blocks), dim3(sweep_block<L>()), 0, s, a);
