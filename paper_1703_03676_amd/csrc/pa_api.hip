@@ -37,7 +37,7 @@ int32_t default_capacity(int32_t R)
 }
 
 struct Layout {
-    size_t spin[2], E[2], M[2], counts, parent, bsum, tbl, stats, mhr, total;
+    size_t spin[2], E[2], M[2], counts, parent, bsum, tbl, stats, parts, mhr, total;
     size_t rep_bytes;
     int32_t capacity, nbins, nblk;
 };
@@ -71,6 +71,7 @@ bool make_layout(const pa_params* p, Layout* lo)
     lo->bsum = take((size_t)lo->nblk * 4 + 4);
     lo->tbl = take((size_t)lo->nbins * 8);
     lo->stats = take(sizeof(DevStats) + (size_t)lo->nbins * 4);
+    lo->parts = take(sizeof(pa::StatsPart) * (size_t)lo->nblk);
     lo->mhr = (p->flags & PA_FLAG_MHR) ? take((size_t)lo->nbins * 40) : o;
     lo->total = o;
     return true;
@@ -90,6 +91,7 @@ struct pa_run {
     int cur;
     uint32_t *counts, *parent, *bsum, *tbl, *hist;
     DevStats* stats;
+    pa::StatsPart* parts;
     DevMhr mhr;
     // host-side run state
     int64_t R_cur;
@@ -104,6 +106,7 @@ struct pa_run {
     std::vector<uint32_t> h_hist;
     uint8_t* pinned;
     size_t pinned_bytes;
+    hipEvent_t ev_rnew = nullptr;  // marks the resampling total in host memory
     std::vector<double> m_beta, m_lnZ;
     std::vector<int64_t> m_R;
 };
@@ -160,7 +163,7 @@ pa_status refresh_stats(pa_run* r, bool record)
     if (!record && r->stats_version == r->version) return PA_OK;
     HIPCHK(pa::launch_stats_reset(r->stats, r->hist, r->nbins, r->stream));
     HIPCHK(pa::launch_stats(r->E[r->cur], r->M[r->cur], (int32_t)r->R_cur, r->N, r->stats, r->hist, r->nbins,
-                            record ? 1 : 0, r->mhr, r->stream));
+                            record ? 1 : 0, r->mhr, r->parts, r->stream));
     const size_t bytes = sizeof(DevStats) + (size_t)r->nbins * 4;
     HIPCHK(hipMemcpyAsync(r->pinned, r->stats, bytes, hipMemcpyDeviceToHost, r->stream));
     HIPCHK(hipStreamSynchronize(r->stream));
@@ -233,6 +236,7 @@ pa_status pa_init(const pa_params* p, void* d_workspace, size_t bytes, void* hip
     r->tbl = (uint32_t*)(ws + lo.tbl);
     r->stats = (DevStats*)(ws + lo.stats);
     r->hist = (uint32_t*)(ws + lo.stats + sizeof(DevStats));
+    r->parts = (pa::StatsPart*)(ws + lo.parts);
     if (p->flags & PA_FLAG_MHR) {
         uint64_t* m = (uint64_t*)(ws + lo.mhr);
         r->mhr.H = m;
@@ -247,6 +251,11 @@ pa_status pa_init(const pa_params* p, void* d_workspace, size_t bytes, void* hip
     if (hipHostMalloc((void**)&r->pinned, r->pinned_bytes, hipHostMallocDefault) != hipSuccess) {
         delete r;
         return PA_ENOMEM;
+    }
+    if (hipEventCreateWithFlags(&r->ev_rnew, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(r->pinned);
+        delete r;
+        return PA_EHIP;
     }
     r->cur = 0;
     r->R_cur = p->R;
@@ -308,17 +317,21 @@ pa_status pa_resample(pa_run* r, double beta_next, pa_resample_info* out)
     HIPCHK(pa::launch_scan_blocks(r->bsum, nblk, r->stats, r->stream));
     uint32_t* rn = (uint32_t*)(r->pinned + r->pinned_bytes - 8);
     HIPCHK(hipMemcpyAsync(rn, &r->stats->r_new, 4, hipMemcpyDeviceToHost, r->stream));
-    HIPCHK(hipStreamSynchronize(r->stream));
+    HIPCHK(hipEventRecord(r->ev_rnew, r->stream));
+    // The parent indices and the copy are queued before the host has seen the
+    // total: they read it on the device, are clamped to the capacity and write
+    // only the other buffer, so a rejected population leaves the run as it was.
+    const int nxt = r->cur ^ 1;
+    HIPCHK(pa::launch_scatter(r->counts, r->bsum, n, r->lo.capacity, r->parent, r->stream));
+    HIPCHK(pa::launch_copy(r->spin[r->cur], r->E[r->cur], r->M[r->cur], r->parent, &r->stats->r_new,
+                           r->lo.capacity, r->lo.rep_bytes, r->spin[nxt], r->E[nxt], r->M[nxt], r->stream));
+    HIPCHK(hipEventSynchronize(r->ev_rnew));
     const int64_t R_new = *rn;
     r->counts_n = n;
     r->stats_version = 0;  // the stats block now holds the resampling total
     if (R_new > r->lo.capacity) return PA_ECAPACITY;
     if (R_new == 0) return PA_EEXTINCT;
 
-    const int nxt = r->cur ^ 1;
-    HIPCHK(pa::launch_scatter(r->counts, r->bsum, n, r->parent, r->stream));
-    HIPCHK(pa::launch_copy(r->spin[r->cur], r->E[r->cur], r->M[r->cur], r->parent, (int32_t)R_new, r->lo.rep_bytes,
-                           r->spin[nxt], r->E[nxt], r->M[nxt], r->stream));
     r->cur = nxt;
     r->R_cur = R_new;
     r->step += 1;
@@ -406,6 +419,7 @@ pa_status pa_state(const pa_run* r, pa_state_info* out)
 pa_status pa_free(pa_run* r)
 {
     if (!r) return PA_OK;
+    if (r->ev_rnew) (void)hipEventDestroy(r->ev_rnew);
     if (r->pinned) (void)hipHostFree(r->pinned);
     delete r;
     return PA_OK;

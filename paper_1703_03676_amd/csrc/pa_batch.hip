@@ -52,6 +52,7 @@ struct RunDev {
     uint32_t* bsum;
     DevStats* stats;  // followed by the energy histogram
     uint32_t* hist;
+    StatsPart* parts;  // per-block partial statistics
     DevMhr mhr;
     int32_t L, N, nbins, capacity, layout, R;
     uint32_t rep_bytes;
@@ -277,52 +278,21 @@ __global__ __launch_bounds__(kBlock) void b_stats(const Item* __restrict__ items
     const bool ok = post_resample(st, res[it.run], &buf, &n);
     if (it.blk * kBlock >= n) return;
     const RunDev& rd = runs[it.run];
-    const int i = it.blk * kBlock + (int)threadIdx.x;
-    uint64_t sE = 0, sE2 = 0, sA = 0, sM2 = 0, m4lo = 0, m4hi = 0;
-    int32_t emin = 0x7FFFFFFF, emax = (int32_t)0x80000000;
-    if (i < n) {
-        const int64_t e = rd.E[buf][i], m = rd.M[buf][i];
-        const uint64_t am = (uint64_t)(m < 0 ? -m : m);
-        const uint64_t m2 = am * am;
-        sE = (uint64_t)e;
-        sE2 = (uint64_t)(e * e);
-        sA = am;
-        sM2 = m2;
-        m4lo = m2 * m2;
-        m4hi = __umul64hi(m2, m2);
-        emin = emax = (int32_t)e;
-        const int b = (int)((e + 2 * rd.N) >> 2);
-        if (b >= 0 && b < rd.nbins) {
-            atomicAdd(&rd.hist[b], 1u);
-            if (st.record && ok) {
-                atomicAdd((unsigned long long*)&rd.mhr.H[b], 1ull);
-                atomicAdd((unsigned long long*)&rd.mhr.SA[b], (unsigned long long)am);
-                atomicAdd((unsigned long long*)&rd.mhr.SM2[b], (unsigned long long)m2);
-                atomic_add_u128(&rd.mhr.SM4[2 * b], &rd.mhr.SM4[2 * b + 1], m4lo, m4hi);
-            }
-        }
-    }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        sE += __shfl_xor(sE, off);
-        sE2 += __shfl_xor(sE2, off);
-        sA += __shfl_xor(sA, off);
-        sM2 += __shfl_xor(sM2, off);
-        const uint64_t olo = __shfl_xor(m4lo, off), ohi = __shfl_xor(m4hi, off);
-        add_u128(m4lo, m4hi, olo, ohi);
-        emin = min(emin, __shfl_xor(emin, off));
-        emax = max(emax, __shfl_xor(emax, off));
-    }
-    if ((threadIdx.x & 63u) == 0u && it.blk * kBlock + (int)(threadIdx.x & ~63u) < n) {
-        DevStats* s = rd.stats;
-        atomicAdd((unsigned long long*)&s->sumE, (unsigned long long)sE);
-        atomicAdd((unsigned long long*)&s->sumE2, (unsigned long long)sE2);
-        atomicAdd((unsigned long long*)&s->sumAbsM, (unsigned long long)sA);
-        atomicAdd((unsigned long long*)&s->sumM2, (unsigned long long)sM2);
-        atomic_add_u128(&s->sumM4_lo, &s->sumM4_hi, m4lo, m4hi);
-        atomicMin(&s->emin, emin);
-        atomicMax(&s->emax, emax);
-    }
+    stats_block(rd.E[buf], rd.M[buf], n, rd.N, it.blk * kBlock, rd.hist, rd.nbins, st.record && ok, rd.mhr,
+                &rd.parts[it.blk]);
+}
+
+// One block per run: sums the partials of b_stats.
+__global__ __launch_bounds__(kBlock) void b_stats_final(const RunDev* __restrict__ runs,
+                                                        const StepDev* __restrict__ steps,
+                                                        const ResultDev* __restrict__ res)
+{
+    const StepDev st = steps[blockIdx.x];
+    if (!st.active) return;
+    int buf, n;
+    post_resample(st, res[blockIdx.x], &buf, &n);
+    const RunDev& rd = runs[blockIdx.x];
+    stats_final(rd.parts, (n + kBlock - 1) / kBlock, rd.stats);
 }
 
 // One block of 64 threads per run: energy moments of the measured population
@@ -430,7 +400,7 @@ bool valid_schedule(const pa_schedule& s)
 
 // Per-run placement inside the batch workspace.
 struct RunLayout {
-    size_t spin[2], E[2], M[2], counts, parent, bsum, mhr;
+    size_t spin[2], E[2], M[2], counts, parent, bsum, parts, mhr;
     size_t stats_off;  // offset of the stats block inside the download area
     size_t tbl_words;  // table capacity in u32
     int32_t capacity, nbins, nblk;
@@ -478,6 +448,7 @@ bool make_batch_layout(const pa_params* runs, int nruns, BatchLayout* bl)
         rl.counts = take((size_t)rl.capacity * 4);
         rl.parent = take((size_t)rl.capacity * 4);
         rl.bsum = take((size_t)rl.nblk * 4 + 4);
+        rl.parts = take(sizeof(StatsPart) * (size_t)rl.nblk);
         rl.mhr = (p.flags & PA_FLAG_MHR) ? take((size_t)rl.nbins * 40) : 0;
         rl.stats_off = dl;
         dl = align_up(dl + sizeof(DevStats) + (size_t)rl.nbins * 4);
@@ -750,6 +721,9 @@ pa_status enqueue_step(pa_batch* b)
     hipLaunchKernelGGL(b_stats, dim3((unsigned)b->n_parent_items), dim3(kBlock), 0, s, items + b->parent_off,
                        b->d_rundev, b->d_steps, b->d_results);
     BCHK(hipGetLastError());
+    hipLaunchKernelGGL(b_stats_final, dim3((unsigned)b->nruns), dim3(kBlock), 0, s, b->d_rundev, b->d_steps,
+                       b->d_results);
+    BCHK(hipGetLastError());
     hipLaunchKernelGGL(b_features, dim3((unsigned)b->nruns), dim3(64), 0, s, b->d_rundev, b->d_steps, b->d_results,
                        b->d_model, b->d_feats);
     BCHK(hipGetLastError());
@@ -919,6 +893,7 @@ static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int
         d.bsum = reinterpret_cast<uint32_t*>(ws + rl.bsum);
         d.stats = reinterpret_cast<DevStats*>(b->d_download + rl.stats_off);
         d.hist = reinterpret_cast<uint32_t*>(b->d_download + rl.stats_off + sizeof(DevStats));
+        d.parts = reinterpret_cast<pa::StatsPart*>(ws + rl.parts);
         if (h.p.flags & PA_FLAG_MHR) {
             uint64_t* m = reinterpret_cast<uint64_t*>(ws + rl.mhr);
             d.mhr = DevMhr{m, m + rl.nbins, m + 2 * (size_t)rl.nbins, m + 3 * (size_t)rl.nbins};

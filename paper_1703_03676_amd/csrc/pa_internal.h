@@ -16,6 +16,15 @@ struct DevStats {
 };
 static_assert(sizeof(DevStats) == 64, "stats block layout");
 
+// Partial statistics of one block of kBlock replicas; the partials of a
+// population are summed by a second kernel into its DevStats.
+struct StatsPart {
+    uint64_t sumE, sumE2, sumAbsM, sumM2, sumM4_lo, sumM4_hi;
+    int32_t emin, emax;
+    uint32_t pad[2];
+};
+static_assert(sizeof(StatsPart) == 64, "partial statistics layout");
+
 // Per-energy accumulators for multi-histogram reweighting (device resident).
 struct DevMhr {
     uint64_t* H;        // [nbins] number of measured replicas per energy
@@ -39,17 +48,21 @@ struct SweepArgs {
 
 // Kernel launchers; each returns the launch status.
 hipError_t launch_sweep(int L, int layout, const SweepArgs& a, hipStream_t s);
+// Statistics of a population (after launch_stats_reset): histogram, range,
+// moment sums; parts holds ceil(n / kBlock) partials.
 hipError_t launch_stats(const int32_t* E, const int32_t* M, int32_t n, int32_t N, DevStats* st,
-                        uint32_t* hist, int32_t nbins, int record, DevMhr mhr, hipStream_t s);
+                        uint32_t* hist, int32_t nbins, int record, DevMhr mhr, StatsPart* parts, hipStream_t s);
 hipError_t launch_counts(const int32_t* E, int32_t n, int32_t N, int32_t bmin, int32_t nwin, const uint32_t* tbl,
                          uint32_t step, uint32_t key0, uint32_t key1, uint32_t* counts, uint32_t* bsum,
                          hipStream_t s);
 hipError_t launch_scan_blocks(uint32_t* bsum, int32_t nblk, DevStats* st, hipStream_t s);
-hipError_t launch_scatter(const uint32_t* counts, const uint32_t* bsum, int32_t n, uint32_t* parent,
+// Parent indices (children beyond cap are dropped) and the replica copy of
+// min(*n_new, cap) children, n_new read on the device.
+hipError_t launch_scatter(const uint32_t* counts, const uint32_t* bsum, int32_t n, int32_t cap, uint32_t* parent,
                           hipStream_t s);
 hipError_t launch_copy(const uint8_t* src, const int32_t* Esrc, const int32_t* Msrc, const uint32_t* parent,
-                       int32_t n_new, size_t rep_bytes, uint8_t* dst, int32_t* Edst, int32_t* Mdst,
-                       hipStream_t s);
+                       const uint32_t* n_new, int32_t cap, size_t rep_bytes, uint8_t* dst, int32_t* Edst,
+                       int32_t* Mdst, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
 hipError_t launch_stats_reset(DevStats* st, uint32_t* hist, int32_t nbins, hipStream_t s);
 

@@ -34,58 +34,19 @@ __global__ __launch_bounds__(sweep_block<L>()) void sweep_kernel(SweepArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Population statistics: histogram n(b), b = (E + 2N) / 4, energy range, and
-// the exact sums of E, E^2, |M|, M^2 (int64) and M^4 (128 bit).  Integer
-// atomics only, so the result does not depend on scheduling order.
+// Population statistics (histogram, energy range, exact moment sums).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void stats_kernel(const int32_t* __restrict__ E, const int32_t* __restrict__ M,
-                                                       int32_t n, int32_t N, DevStats* st, uint32_t* hist,
-                                                       int32_t nbins, int record, DevMhr mhr)
+                                                       int32_t n, int32_t N, uint32_t* hist, int32_t nbins,
+                                                       int record, DevMhr mhr, StatsPart* parts)
 {
-    const int i = (int)(blockIdx.x * kBlock + threadIdx.x);
-    uint64_t sE = 0, sE2 = 0, sA = 0, sM2 = 0, m4lo = 0, m4hi = 0;
-    int32_t emin = 0x7FFFFFFF, emax = (int32_t)0x80000000;
-    if (i < n) {
-        const int64_t e = E[i], m = M[i];
-        const uint64_t am = (uint64_t)(m < 0 ? -m : m);
-        const uint64_t m2 = am * am;
-        sE = (uint64_t)e;
-        sE2 = (uint64_t)(e * e);
-        sA = am;
-        sM2 = m2;
-        m4lo = m2 * m2;
-        m4hi = __umul64hi(m2, m2);
-        emin = emax = (int32_t)e;
-        const int b = (int)((e + 2 * N) >> 2);
-        if (b >= 0 && b < nbins) atomicAdd(&hist[b], 1u);
-        if (record && b >= 0 && b < nbins) {
-            atomicAdd((unsigned long long*)&mhr.H[b], 1ull);
-            atomicAdd((unsigned long long*)&mhr.SA[b], (unsigned long long)am);
-            atomicAdd((unsigned long long*)&mhr.SM2[b], (unsigned long long)m2);
-            atomic_add_u128(&mhr.SM4[2 * b], &mhr.SM4[2 * b + 1], m4lo, m4hi);
-        }
-    }
-    // wave reduction
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        sE += __shfl_xor(sE, off);
-        sE2 += __shfl_xor(sE2, off);
-        sA += __shfl_xor(sA, off);
-        sM2 += __shfl_xor(sM2, off);
-        const uint64_t olo = __shfl_xor(m4lo, off), ohi = __shfl_xor(m4hi, off);
-        add_u128(m4lo, m4hi, olo, ohi);
-        emin = min(emin, __shfl_xor(emin, off));
-        emax = max(emax, __shfl_xor(emax, off));
-    }
-    if ((threadIdx.x & 63u) == 0u && (int)(blockIdx.x * kBlock + (threadIdx.x & ~63u)) < n) {
-        atomicAdd((unsigned long long*)&st->sumE, (unsigned long long)sE);
-        atomicAdd((unsigned long long*)&st->sumE2, (unsigned long long)sE2);
-        atomicAdd((unsigned long long*)&st->sumAbsM, (unsigned long long)sA);
-        atomicAdd((unsigned long long*)&st->sumM2, (unsigned long long)sM2);
-        atomic_add_u128(&st->sumM4_lo, &st->sumM4_hi, m4lo, m4hi);
-        atomicMin(&st->emin, emin);
-        atomicMax(&st->emax, emax);
-    }
+    stats_block(E, M, n, N, (int32_t)(blockIdx.x * kBlock), hist, nbins, record != 0, mhr, &parts[blockIdx.x]);
+}
+
+__global__ __launch_bounds__(kBlock) void stats_final_kernel(const StatsPart* __restrict__ parts, int32_t nparts,
+                                                             DevStats* st)
+{
+    stats_final(parts, nparts, st);
 }
 
 __global__ void stats_reset_kernel(DevStats* st, uint32_t* hist, int32_t nbins)
@@ -158,24 +119,31 @@ __global__ __launch_bounds__(1024) void scan_blocks_kernel(uint32_t* bsum, int32
     if (t == 1023) st->r_new = part[1023];
 }
 
+// Parent index of every child; children beyond `cap` are not written (the
+// caller rejects such a population).
 __global__ __launch_bounds__(kBlock) void scatter_kernel(const uint32_t* __restrict__ counts,
-                                                         const uint32_t* __restrict__ bsum, int32_t n,
+                                                         const uint32_t* __restrict__ bsum, int32_t n, uint32_t cap,
                                                          uint32_t* __restrict__ parent)
 {
     const int j = (int)(blockIdx.x * kBlock + threadIdx.x);
     const uint32_t c = (j < n) ? counts[j] : 0u;
     uint32_t total;
     const uint32_t off = bsum[blockIdx.x] + block_exclusive_scan(c, &total);
-    for (uint32_t k = 0; k < c; ++k) parent[off + k] = (uint32_t)j;
+    for (uint32_t k = 0; k < c && off + k < cap; ++k) parent[off + k] = (uint32_t)j;
 }
 
+// Replica copy child <- parent[child] for child < min(*n_new, cap); the size
+// of the new population is read on the device, so the copy can be queued
+// before the host has seen it.
 __global__ __launch_bounds__(kBlock) void copy_kernel(const uint4* __restrict__ src, const int32_t* __restrict__ Es,
                                                       const int32_t* __restrict__ Ms,
-                                                      const uint32_t* __restrict__ parent, int32_t n_new,
+                                                      const uint32_t* __restrict__ parent,
+                                                      const uint32_t* __restrict__ n_new, uint32_t cap,
                                                       uint32_t chunks, uint4* __restrict__ dst,
                                                       int32_t* __restrict__ Ed, int32_t* __restrict__ Md)
 {
-    const size_t total = (size_t)n_new * chunks;
+    const uint32_t nn = min(*n_new, cap);
+    const size_t total = (size_t)nn * chunks;
     for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < total; i += (size_t)gridDim.x * kBlock) {
         const uint32_t child = (uint32_t)(i / chunks), ch = (uint32_t)(i % chunks);
         const uint32_t p = parent[child];
@@ -214,14 +182,14 @@ hipError_t launch_sweep(int L, int layout, const SweepArgs& a, hipStream_t s)
 }
 
 hipError_t launch_stats(const int32_t* E, const int32_t* M, int32_t n, int32_t N, DevStats* st, uint32_t* hist,
-                        int32_t nbins, int record, DevMhr mhr, hipStream_t s)
+                        int32_t nbins, int record, DevMhr mhr, StatsPart* parts, hipStream_t s)
 {
     const int blocks = (n + kBlock - 1) / kBlock;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(stats_kernel, dim3(blocks), dim3(kBlock), 0, s, E, M, n, N, st, hist, nbins, record, mhr);
+    hipLaunchKernelGGL(stats_kernel, dim3(blocks), dim3(kBlock), 0, s, E, M, n, N, hist, nbins, record, mhr, parts);
+    hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(kBlock), 0, s, (const StatsPart*)parts, blocks, st);
     return hipGetLastError();
 }
-
 hipError_t launch_stats_reset(DevStats* st, uint32_t* hist, int32_t nbins, hipStream_t s)
 {
     const int blocks = std::min((nbins + kBlock - 1) / kBlock, 1024);
@@ -253,23 +221,25 @@ hipError_t launch_scan_blocks(uint32_t* bsum, int32_t nblk, DevStats* st, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const uint32_t* counts, const uint32_t* bsum, int32_t n, uint32_t* parent, hipStream_t s)
+hipError_t launch_scatter(const uint32_t* counts, const uint32_t* bsum, int32_t n, int32_t cap, uint32_t* parent,
+                          hipStream_t s)
 {
     const int blocks = (n + kBlock - 1) / kBlock;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(kBlock), 0, s, counts, bsum, n, parent);
+    hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(kBlock), 0, s, counts, bsum, n, (uint32_t)cap, parent);
     return hipGetLastError();
 }
 
 hipError_t launch_copy(const uint8_t* src, const int32_t* Esrc, const int32_t* Msrc, const uint32_t* parent,
-                       int32_t n_new, size_t rep_bytes, uint8_t* dst, int32_t* Edst, int32_t* Mdst, hipStream_t s)
+                       const uint32_t* n_new, int32_t cap, size_t rep_bytes, uint8_t* dst, int32_t* Edst,
+                       int32_t* Mdst, hipStream_t s)
 {
     const uint32_t chunks = (uint32_t)(rep_bytes / 16);
-    const size_t total = (size_t)n_new * chunks;
+    const size_t total = (size_t)cap * chunks;
     if (total == 0) return hipSuccess;
     const size_t blocks = std::min<size_t>((total + kBlock - 1) / kBlock, 8192);
     hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, reinterpret_cast<const uint4*>(src),
-                       Esrc, Msrc, parent, n_new, chunks, reinterpret_cast<uint4*>(dst), Edst, Mdst);
+                       Esrc, Msrc, parent, n_new, (uint32_t)cap, chunks, reinterpret_cast<uint4*>(dst), Edst, Mdst);
     return hipGetLastError();
 }
 
