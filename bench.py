@@ -37,13 +37,21 @@ L, R, THETA, DBETA, NSTEPS = 64, 20000, 100, 0.005, 200
 VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 SLOTS_PER_FLIP = 3.5
 PROFILE = os.path.join(ROOT, "profiles", "sweep_kernel_L64_R20000_theta100.md")
-KERNEL_SRC = os.path.join(ROOT, "paper_1703_03676_amd", "csrc", "pa_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1703_03676_amd", "csrc", f) for f in ("pa_device.h", "pa_kernels.hip")]
+
+
+def kernel_source_hash():
+    """First 16 hex digits of the sha256 of the sweep kernel's sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
     """HBM bytes per sweep launch from the committed counter profile, or None
     when the kernel source has changed since the counters were taken."""
-    import hashlib
     import re
     try:
         txt = open(PROFILE).read()
@@ -51,8 +59,7 @@ def measured_traffic():
         val = float(re.search(r"traffic_bytes_per_launch = ([0-9.e+]+)", txt).group(1))
     except (OSError, AttributeError, ValueError):
         return None
-    have = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
-    return val if have == want else None
+    return val if kernel_source_hash() == want else None
 
 
 def one_run(pa, torch, seed, layout, sweep_events=None):

@@ -171,6 +171,13 @@ const char* pa_last_error(const pa_run* r);
  * Any pointer may be NULL. */
 pa_status pa_download_population(pa_run* r, int8_t* spins, int32_t* E, int32_t* M);
 
+/* Copy n selected replicas to host memory: idx[k] (0 <= idx[k] < R_i) is
+ * the replica whose spins go to spins[k] (int8 +-1, row-major [L][L]) and
+ * whose energy and magnetisation go to E[k], M[k].  For sampled checks of
+ * populations too large to download whole.  E and M may be NULL.
+ * PA_EINVAL if an index is out of range (nothing is copied). */
+pa_status pa_download_replicas(pa_run* r, const int32_t* idx, int32_t n, int8_t* spins, int32_t* E, int32_t* M);
+
 /* Replace the population by R_cur host configurations (int8 +-1, row-major)
  * and set the counters that key the random streams.  E and M are recomputed on
  * the device from the spins.  Errors: PA_EINVAL (R_cur out of [1, capacity],

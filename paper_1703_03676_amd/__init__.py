@@ -94,6 +94,7 @@ SIGNATURES = {
     "pa_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "pa_last_error": (ctypes.c_char_p, [_vp]),
     "pa_download_population": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "pa_download_replicas": (ctypes.c_int, [_vp, _vp, ctypes.c_int32, _vp, _vp, _vp]),
     "pa_upload_population": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, ctypes.c_int32, ctypes.c_uint64,
                                             ctypes.c_double, ctypes.c_double]),
     "pa_download_counts": (ctypes.c_int, [_vp, _vp, _P(ctypes.c_int32)]),
@@ -250,6 +251,24 @@ class Run:
         E = np.empty(n, np.int32)
         M = np.empty(n, np.int32)
         _check(lib().pa_download_population(self.h, _ptr(s), _ptr(E), _ptr(M)), self.h)
+        return s, E, M
+
+    def download_energies(self):
+        """(E int32 [R_i], M int32 [R_i]) without the spins."""
+        n = self.state()["R"]
+        E = np.empty(n, np.int32)
+        M = np.empty(n, np.int32)
+        _check(lib().pa_download_population(self.h, None, _ptr(E), _ptr(M)), self.h)
+        return E, M
+
+    def download_replicas(self, idx):
+        """Spins (int8 [n, L, L]), E and M of the replicas idx."""
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        n = len(idx)
+        s = np.empty((n, self.L, self.L), np.int8)
+        E = np.empty(n, np.int32)
+        M = np.empty(n, np.int32)
+        _check(lib().pa_download_replicas(self.h, _ptr(idx), n, _ptr(s), _ptr(E), _ptr(M)), self.h)
         return s, E, M
 
     def upload_population(self, spins, step=0, sweeps=0, beta=0.0, lnZ=0.0):

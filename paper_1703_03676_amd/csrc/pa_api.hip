@@ -446,6 +446,33 @@ pa_status pa_download_population(pa_run* r, int8_t* spins, int32_t* E, int32_t* 
     return PA_OK;
 }
 
+pa_status pa_download_replicas(pa_run* r, const int32_t* idx, int32_t n, int8_t* spins, int32_t* E, int32_t* M)
+{
+    pa_status st = usable(r);
+    if (st != PA_OK) return st;
+    if (n < 0 || (n > 0 && (!idx || !spins))) return PA_EINVAL;
+    for (int32_t k = 0; k < n; ++k)
+        if (idx[k] < 0 || idx[k] >= r->R_cur) return PA_EINVAL;
+    const size_t rb = r->lo.rep_bytes;
+    std::vector<uint8_t> raw((size_t)n * rb);
+    std::vector<int32_t> e((size_t)n), m((size_t)n);
+    for (int32_t k = 0; k < n; ++k) {
+        const size_t j = (size_t)idx[k];
+        HIPCHK(hipMemcpyAsync(raw.data() + (size_t)k * rb, r->spin[r->cur] + j * rb, rb, hipMemcpyDeviceToHost,
+                              r->stream));
+        HIPCHK(hipMemcpyAsync(&e[(size_t)k], r->E[r->cur] + j, 4, hipMemcpyDeviceToHost, r->stream));
+        HIPCHK(hipMemcpyAsync(&m[(size_t)k], r->M[r->cur] + j, 4, hipMemcpyDeviceToHost, r->stream));
+    }
+    HIPCHK(hipStreamSynchronize(r->stream));
+    if (r->p.layout == PA_SPIN_INT8)
+        std::memcpy(spins, raw.data(), raw.size());
+    else
+        host::bits_to_int8(reinterpret_cast<const uint32_t*>(raw.data()), r->L, (size_t)n, spins);
+    if (E) std::memcpy(E, e.data(), e.size() * 4);
+    if (M) std::memcpy(M, m.data(), m.size() * 4);
+    return PA_OK;
+}
+
 pa_status pa_upload_population(pa_run* r, int32_t R_cur, const int8_t* spins, int32_t step, uint64_t sweeps,
                                double beta, double lnZ)
 {

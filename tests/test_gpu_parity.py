@@ -118,6 +118,34 @@ def test_resample_matches_oracle(L, layout):
         assert st["lnZ"] == o.lnZ and st["step"] == o.step and st["beta"] == o.beta
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("L,R,kind", [(64, 600, "ordered"), (64, 600, "mixed"), (128, 300, "mixed")])
+def test_statistics_windows_and_multi_histogram(L, R, kind, layout):
+    """Population statistics and the multi-histogram accumulators for narrow
+    per-block energy windows (ordered) and for windows wider than the
+    kernels' LDS tables (mixed: ordered and random replicas in one block),
+    over several blocks with a ragged last one."""
+    print("case stats L=%d R=%d %s layout=%s" % (L, R, kind, layout), flush=True)
+    if kind == "ordered":
+        spins = inputs.ordered_spins(R, L, seed=21, n_flipped_max=40)
+    else:
+        spins = inputs.mixed_spins(R, L, seed=22)
+    g = pa.Run(L, R, seed=13, layout=layout, mhr=True)
+    o = oracle.Run(L, R, seed=13)
+    g.upload_population(spins, step=2, sweeps=5, beta=0.35, lnZ=3.0)
+    o.set_population(spins, step=2, sweeps=5, beta=0.35, lnZ=3.0)
+    _same_obs(g.observables(), o.measure())
+    for beta in (0.36, 0.4):
+        assert g.resample(beta) == o.resample(beta)
+        g.sweep(1)
+        o.sweep(1)
+        _same_obs(g.observables(), o.measure())
+    betas = np.linspace(0.3, 0.5, 11)
+    for go, oo in zip(g.reweight(betas), o.reweight(betas)):
+        for k in ("e", "C", "abs_m", "m2", "m4", "betaF_per_N", "S_per_N"):
+            assert _close(go[k], oo[k], 1e-12), (k, go["beta"], go[k], oo[k])
+
+
 def _config1_trace(run, nsteps, theta, dbeta, measure):
     trace = [measure()]
     for i in range(1, nsteps + 1):
@@ -181,6 +209,42 @@ def test_config2_full_size_sampled(layout):
     assert np.array_equal(s.sum(axis=(1, 2)), gM)
     obs = g.observables()
     assert obs["sumE"] == int(gE.astype(np.int64).sum()) and obs["R"] == n
+
+
+def _energy_of(spins):
+    s = spins.astype(np.int32)
+    return -(s * (np.roll(s, -1, 2) + np.roll(s, -1, 1))).sum(axis=(1, 2)), s.sum(axis=(1, 2))
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("L,R,theta,beta", [(128, 50000, 2, 0.44), (256, 100000, 1, 0.44)])
+def test_full_size_lds_path_sampled(L, R, theta, beta, layout):
+    """The LDS-path sweep at the full L=128 (R=50000) and L=256 (R=100000)
+    workload sizes, in the benchmark's launch configuration: sampled replicas
+    are swept again by the oracle alone at their slots; every replica's E and
+    M sum to the population statistics."""
+    print("case full-size L=%d R=%d layout=%s" % (L, R, layout), flush=True)
+    g = pa.Run(L, R, seed=2, layout=layout)
+    g.resample(beta)
+    st = g.state()
+    n = st["R"]
+    rng = np.random.default_rng(1)
+    slots = np.unique(np.concatenate([[0, 1, 63, 64, n - 1], rng.integers(0, n, 4)])).astype(np.int32)
+    pre, pE, pM = g.download_replicas(slots)
+    assert np.array_equal(_energy_of(pre)[0], pE) and np.array_equal(_energy_of(pre)[1], pM)
+    g.sweep(theta)
+    gs, gE, gM = g.download_replicas(slots)
+    so = oracle.Run(L, len(slots), seed=2)
+    so.set_population(pre, step=st["step"], sweeps=st["sweeps"], beta=st["beta"])
+    so.set_slots(slots)
+    so.sweep(theta)
+    ss, sE, sM = so.get_population()
+    assert np.array_equal(ss, gs) and np.array_equal(sE, gE) and np.array_equal(sM, gM)
+    E, M = g.download_energies()
+    obs = g.observables()
+    assert obs["R"] == n == len(E)
+    assert obs["sumE"] == int(E.astype(np.int64).sum())
+    assert obs["sumAbsM"] == int(np.abs(M.astype(np.int64)).sum())
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
