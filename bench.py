@@ -3,14 +3,16 @@
 Workload (the paper's sample-program defaults): L = 64, R = 20000, theta = 100,
 beta 0 -> 1 in 200 fixed steps of 0.005, random initial spins.  One benchmark
 "step" is one complete PA run: initial state, then 200 x (resample, theta
-sweeps, measurement), all through the C ABI.  The metric is attempted spin
-flips per ns over the whole run, L^2 theta sum_i R_i / t_run (the inverse of
-the paper's time per spin flip).
+sweeps, measurement), through the C ABI's pa_anneal (the schedule in one call,
+one host round trip per temperature step).  The metric is attempted spin flips
+per ns over the whole run, L^2 theta sum_i R_i / t_run (the inverse of the
+paper's time per spin flip).  The same runs driven one call at a time from
+Python are reported beside it.
 
-Prints one JSON line.  The dominant kernel (the sweep) is timed with HIP events
-on the run's stream; its roofline is the VALU issue rate (the sweep is bound by
-integer ALU work for the random numbers, not by HBM).  The CPU oracle is timed
-on a bounded sample of the same workload.
+Prints one JSON line.  The dominant kernel (the sweep) is timed by the library
+with HIP events on the run's stream, inside the timed runs; its roofline is the
+VALU issue rate (the sweep is bound by integer ALU work for the random numbers,
+not by HBM).  The CPU oracle is timed on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -63,6 +65,8 @@ def measured_traffic():
 
 
 def one_run(pa, torch, seed, layout, sweep_events=None):
+    """One full run through the single-step calls (pa_resample, pa_sweep,
+    pa_observables per temperature step, from Python)."""
     run = pa.Run(L, R, seed=seed, layout=layout)
     stream = torch.cuda.current_stream()
     run.observables()
@@ -85,20 +89,37 @@ def one_run(pa, torch, seed, layout, sweep_events=None):
     return flips, last
 
 
+def anneal_run(pa, seed, layout, sweeps=None):
+    """One full run through pa_anneal (the whole schedule in one call, one
+    host round trip per temperature step).  The library times every sweep
+    launch with HIP events on the run's stream; (ms, flips) pairs are appended
+    to `sweeps`."""
+    run = pa.Run(L, R, seed=seed, layout=layout)
+    run.observables()
+    obs, ms = run.anneal(beta_f=1.0, dbeta=DBETA, theta=THETA, mode="fixed", sweep_times=True)
+    run.close()
+    assert len(obs) == NSTEPS
+    flips = [L * L * THETA * o["R"] for o in obs]
+    if sweeps is not None:
+        sweeps.extend(zip(ms, flips))
+    return sum(flips), obs[-1]
+
+
 def time_layout(pa, torch, layout, steps, warmup):
+    """Timed full runs through pa_anneal (the headline)."""
     for w in range(warmup):
-        one_run(pa, torch, 1 + w % 3, layout)
+        anneal_run(pa, 1 + w % 3, layout)
     torch.cuda.synchronize()
-    events = []
+    sweeps = []
     total_flips = 0
     t0 = time.perf_counter()
     for k in range(steps):
-        f, last = one_run(pa, torch, 1 + k % 3, layout, events)
+        f, last = anneal_run(pa, 1 + k % 3, layout, sweeps)
         total_flips += f
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    sweep_ms = [a.elapsed_time(b) for a, b, _ in events]
-    sweep_flips = [L * L * THETA * n for _, _, n in events]
+    sweep_ms = [m for m, _ in sweeps]
+    sweep_flips = [f for _, f in sweeps]
     return {
         "flips": total_flips,
         "seconds": t,
@@ -110,6 +131,24 @@ def time_layout(pa, torch, layout, steps, warmup):
         "e_final": last["e"],
         "betaF_per_N_final": last["betaF_per_N"],
     }
+
+
+def time_step_calls(pa, torch, layout, steps):
+    """The same runs driven one C-ABI call at a time from Python, for
+    comparison with pa_anneal (not the headline)."""
+    one_run(pa, torch, 1, layout)
+    torch.cuda.synchronize()
+    events = []
+    total_flips = 0
+    t0 = time.perf_counter()
+    for k in range(steps):
+        f, _ = one_run(pa, torch, 1 + k % 3, layout, events)
+        total_flips += f
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    sweep_ms = [a.elapsed_time(b) for a, b, _ in events]
+    return {"flips_per_ns": total_flips / (t * 1e9), "ms_per_run": 1e3 * t / steps,
+            "sweep_ms_avg": sum(sweep_ms) / len(sweep_ms)}
 
 
 def cpu_baseline(seconds_target=15.0):
@@ -325,6 +364,7 @@ def main():
         return 0
     layouts = args.layouts.split(",")
     res = {lay: time_layout(pa, torch, lay, args.steps, args.warmup) for lay in layouts}
+    steps_cmp = time_step_calls(pa, torch, layouts[0], 2)
     head = res[layouts[0]]
     achieved = head["sweep_flips_avg"] * SLOTS_PER_FLIP / (head["sweep_ms_avg"] * 1e-3)
     out = {
@@ -343,7 +383,7 @@ def main():
         "config": {
             "workload": "population annealing, 2D Ising L=64 periodic, R=20000, theta=100, "
                         "beta 0->1 fixed dbeta=0.005 (200 steps), random initial spins, "
-                        "spin store: %s; one step = one full PA run" % layouts[0],
+                        "spin store: %s; one step = one full PA run (pa_anneal)" % layouts[0],
             "L": L, "R": R, "theta": THETA, "dbeta": DBETA, "temperature_steps": NSTEPS,
             "layout": layouts[0],
         },
@@ -362,6 +402,7 @@ def main():
         },
         "layouts": {lay: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
                     for lay, r in res.items()},
+        "step_calls_%s" % layouts[0]: {k: round(v, 4) for k, v in steps_cmp.items()},
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

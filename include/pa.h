@@ -213,6 +213,28 @@ typedef struct {
     int32_t mode;        /* pa_step_mode */
 } pa_schedule;
 
+/* Single run: temperature steps of Sec. 2.1 from the current state until
+ * beta_f or max_steps steps.  Each step takes the next inverse temperature
+ * (PA_STEP_FIXED: beta_i = i * dbeta, the last one beta_f; PA_STEP_ADAPTIVE:
+ * the rule of Sec. 2.3 as in pa_adapt_beta), resamples (Eq. (Q), Eq.
+ * (resampling factors)), runs theta sweeps (Sec. 3) and measures (Eqs.
+ * (observables), (free energy), (entropy)); with PA_FLAG_MHR the measurement
+ * is recorded for pa_reweight.  The results are those of the same sequence
+ * of single calls (pa_adapt_beta, pa_resample, pa_sweep, pa_observables), bit
+ * for bit.  The device work of a step is queued before the host has seen the
+ * new population size, which the kernels read on the device, so a step costs
+ * one host round trip.
+ *   out[k] (k < cap) receives the observables after step k (out may be NULL
+ *   if cap is 0); *nsteps (may be NULL) the number of steps completed.
+ *   sweep_ms (may be NULL, else cap floats): sweep_ms[k] receives the duration
+ *   of step k's sweep launch, measured with HIP events on the run's stream.
+ * Errors: PA_EINVAL (invalid schedule, PA_STEP_LEARNED, beta_f below the
+ * current beta, no adaptive step reaching alpha_star, sweep counter
+ * overflow); PA_ECAPACITY / PA_EEXTINCT (the run stays at the last completed
+ * step); PA_ESTATE, PA_EHIP.  Synchronises the stream. */
+pa_status pa_anneal(pa_run* r, const pa_schedule* s, int32_t max_steps, pa_obs* out, float* sweep_ms, int32_t cap,
+                    int32_t* nsteps);
+
 typedef struct pa_batch pa_batch;  /* opaque host handle */
 
 /* Device workspace for nruns runs; 0 if any parameter set is invalid. */

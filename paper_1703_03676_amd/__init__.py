@@ -84,6 +84,7 @@ SIGNATURES = {
     "pa_workspace_bytes": (ctypes.c_size_t, [_P(Params)]),
     "pa_init": (ctypes.c_int, [_P(Params), _vp, ctypes.c_size_t, _vp, _P(_vp)]),
     "pa_sweep": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pa_anneal": (ctypes.c_int, [_vp, _P(Schedule), ctypes.c_int32, _vp, _vp, ctypes.c_int32, _P(ctypes.c_int32)]),
     "pa_resample": (ctypes.c_int, [_vp, ctypes.c_double, _P(ResampleInfo)]),
     "pa_adapt_beta": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, _P(ctypes.c_double), _P(ctypes.c_double)]),
     "pa_alpha": (ctypes.c_int, [_vp, ctypes.c_double, _P(ctypes.c_double)]),
@@ -212,6 +213,23 @@ class Run:
     # --- the method -------------------------------------------------------
     def sweep(self, nsweeps):
         _check(lib().pa_sweep(self.h, int(nsweeps)), self.h)
+
+    def anneal(self, beta_f=1.0, dbeta=0.0, alpha_star=0.0, theta=1, mode="fixed", max_steps=1 << 30, cap=4096,
+               sweep_times=False):
+        """Temperature steps until beta_f (fixed dbeta or adaptive alpha_star),
+        each resample + theta sweeps + measurement; returns the observables
+        after every step (at most cap of them), and with sweep_times also the
+        sweep launch durations in ms."""
+        sched = make_schedule(beta_f=beta_f, dbeta=dbeta, alpha_star=alpha_star, theta=theta, mode=mode)
+        out = (Obs * cap)()
+        ms = np.zeros(cap, np.float32)
+        n = ctypes.c_int32()
+        st = lib().pa_anneal(self.h, ctypes.byref(sched), int(max_steps), ctypes.cast(out, _vp),
+                             _ptr(ms) if sweep_times else None, int(cap), ctypes.byref(n))
+        k = min(n.value, cap)
+        res = [o.as_dict() for o in out[:k]]
+        _check(st, self.h)
+        return (res, ms[:k].tolist()) if sweep_times else res
 
     def resample(self, beta_next):
         info = ResampleInfo()

@@ -107,6 +107,7 @@ struct pa_run {
     uint8_t* pinned;
     size_t pinned_bytes;
     hipEvent_t ev_rnew = nullptr;  // marks the resampling total in host memory
+    hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;  // sweep timing in pa_anneal (created on first use)
     std::vector<double> m_beta, m_lnZ;
     std::vector<int64_t> m_R;
 };
@@ -162,8 +163,8 @@ pa_status refresh_stats(pa_run* r, bool record)
 {
     if (!record && r->stats_version == r->version) return PA_OK;
     HIPCHK(pa::launch_stats_reset(r->stats, r->hist, r->nbins, r->stream));
-    HIPCHK(pa::launch_stats(r->E[r->cur], r->M[r->cur], (int32_t)r->R_cur, r->N, r->stats, r->hist, r->nbins,
-                            record ? 1 : 0, r->mhr, r->parts, r->stream));
+    HIPCHK(pa::launch_stats(r->E[r->cur], r->M[r->cur], (int32_t)r->R_cur, nullptr, r->N, r->stats, r->hist,
+                            r->nbins, record ? 1 : 0, r->mhr, r->parts, r->stream));
     const size_t bytes = sizeof(DevStats) + (size_t)r->nbins * 4;
     HIPCHK(hipMemcpyAsync(r->pinned, r->stats, bytes, hipMemcpyDeviceToHost, r->stream));
     HIPCHK(hipStreamSynchronize(r->stream));
@@ -347,6 +348,135 @@ pa_status pa_resample(pa_run* r, double beta_next, pa_resample_info* out)
     return PA_OK;
 }
 
+pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs* out, float* sweep_ms, int32_t cap,
+                    int32_t* nsteps)
+{
+    if (nsteps) *nsteps = 0;
+    pa_status st = usable(r);
+    if (st != PA_OK) return st;
+    if (!sc || max_steps < 0 || cap < 0 || (cap > 0 && !out) || sc->theta < 0 || !std::isfinite(sc->beta_f) ||
+        sc->beta_f < r->beta)
+        return PA_EINVAL;
+    if (sc->mode == PA_STEP_FIXED) {
+        if (!(sc->dbeta > 0.0) || !std::isfinite(sc->dbeta)) return PA_EINVAL;
+    } else if (sc->mode == PA_STEP_ADAPTIVE) {
+        if (!(sc->alpha_star > 0.0 && sc->alpha_star < 1.0)) return PA_EINVAL;
+    } else {
+        return PA_EINVAL;
+    }
+    const bool record = (r->p.flags & PA_FLAG_MHR) != 0;
+    st = refresh_stats(r, false);
+    if (st != PA_OK) return st;
+    if (sweep_ms && cap > 0 && !r->ev_t0) {
+        HIPCHK(hipEventCreate(&r->ev_t0));
+        HIPCHK(hipEventCreate(&r->ev_t1));
+    }
+    uint32_t k0, k1;
+    key_of(r, &k0, &k1);
+    std::vector<double> w;
+    int32_t done = 0;
+    while (done < max_steps && r->beta < sc->beta_f) {
+        if (r->sweeps + (uint64_t)sc->theta >= ((uint64_t)1 << 31)) return PA_EINVAL;
+        // next inverse temperature from the host copy of the current statistics
+        const host::Hist h = window(r);
+        double bn;
+        if (sc->mode == PA_STEP_FIXED) {
+            const int64_t nb = std::max<int64_t>(1, std::llround(sc->beta_f / sc->dbeta));
+            const int64_t i = (int64_t)r->step + 1;
+            bn = (i >= nb) ? sc->beta_f : (double)i * sc->dbeta;
+            if (bn > sc->beta_f) bn = sc->beta_f;
+            if (bn < r->beta) bn = r->beta;
+        } else if (!host::adapt_beta(h, r->p.R, r->R_cur, r->beta, sc->beta_f, sc->alpha_star, &bn, nullptr, w)) {
+            return PA_EINVAL;
+        }
+        // Eq. (Q) and the tables of Eq. (resampling factors)
+        const int bmin = h.bmin, nwin = h.bmax - h.bmin + 1;
+        uint32_t* tab = (uint32_t*)r->pinned;
+        const double lnQ = host::resample_tables(h, r->p.R, r->R_cur, bn - r->beta, tab, w);
+        HIPCHK(hipMemcpyAsync(r->tbl, tab, (size_t)nwin * 8, hipMemcpyHostToDevice, r->stream));
+        // The whole step is queued before the host sees the new population
+        // size: resampling into the other buffer, the sweeps and the statistics
+        // there all read it on the device.  A rejected step leaves `cur` as is.
+        const int32_t n = (int32_t)r->R_cur;
+        const int32_t nblk = (n + pa::kBlock - 1) / pa::kBlock;
+        const int nxt = r->cur ^ 1;
+        const uint32_t* n_dev = &r->stats->r_new;
+        HIPCHK(pa::launch_counts(r->E[r->cur], n, r->N, bmin, nwin, r->tbl, (uint32_t)(r->step + 1), k0, k1,
+                                 r->counts, r->bsum, r->stream));
+        HIPCHK(pa::launch_scan_blocks(r->bsum, nblk, r->stats, r->stream));
+        HIPCHK(pa::launch_scatter(r->counts, r->bsum, n, r->lo.capacity, r->parent, r->stream));
+        HIPCHK(pa::launch_copy(r->spin[r->cur], r->E[r->cur], r->M[r->cur], r->parent, n_dev, r->lo.capacity,
+                               r->lo.rep_bytes, r->spin[nxt], r->E[nxt], r->M[nxt], r->stream));
+        if (sc->theta > 0) {
+            pa::SweepArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.spin = r->spin[nxt];
+            a.E = r->E[nxt];
+            a.M = r->M[nxt];
+            a.n_rep = r->lo.capacity;
+            a.n_dev = n_dev;
+            a.nsweeps = sc->theta;
+            a.g0 = (uint32_t)r->sweeps;
+            a.key0 = k0;
+            a.key1 = k1;
+            host::thresholds(bn, &a.t2h, &a.t2l, &a.t4h, &a.t4l);
+            const bool timed = sweep_ms && done < cap;
+            if (timed) HIPCHK(hipEventRecord(r->ev_t0, r->stream));
+            HIPCHK(pa::launch_sweep(r->L, r->p.layout, a, r->stream));
+            if (timed) HIPCHK(hipEventRecord(r->ev_t1, r->stream));
+        }
+        HIPCHK(pa::launch_stats_reset(r->stats, r->hist, r->nbins, r->stream));
+        HIPCHK(pa::launch_stats(r->E[nxt], r->M[nxt], r->lo.capacity, n_dev, r->N, r->stats, r->hist, r->nbins, 0,
+                                r->mhr, r->parts, r->stream));
+        const size_t bytes = sizeof(DevStats) + (size_t)r->nbins * 4;
+        HIPCHK(hipMemcpyAsync(r->pinned, r->stats, bytes, hipMemcpyDeviceToHost, r->stream));
+        HIPCHK(hipStreamSynchronize(r->stream));
+        DevStats hs;
+        std::memcpy(&hs, r->pinned, sizeof(DevStats));
+        const int64_t R_new = hs.r_new;
+        r->counts_n = n;
+        if (R_new > r->lo.capacity || R_new == 0) {
+            r->stats_version = 0;  // the statistics block holds the rejected population
+            return R_new == 0 ? PA_EEXTINCT : PA_ECAPACITY;
+        }
+        r->cur = nxt;
+        r->R_cur = R_new;
+        r->step += 1;
+        r->beta = bn;
+        r->lnZ += lnQ;
+        r->lnQ_last = lnQ;
+        r->sweeps += (uint64_t)sc->theta;
+        r->version += 2;
+        r->h_stats = hs;
+        std::memcpy(r->h_hist.data(), r->pinned + sizeof(DevStats), (size_t)r->nbins * 4);
+        if (hs.emin < -2 * r->N || hs.emax > 2 * r->N || hs.emin > hs.emax) {
+            r->broken = true;
+            r->last_error = "population energies out of range";
+            return PA_ESTATE;
+        }
+        r->stats_version = r->version;
+        // measurement (Eq. (observables)); the multi-histogram record is queued
+        // without a wait, since its statistics equal the ones just read
+        if (record) {
+            HIPCHK(pa::launch_stats_reset(r->stats, r->hist, r->nbins, r->stream));
+            HIPCHK(pa::launch_stats(r->E[r->cur], r->M[r->cur], (int32_t)r->R_cur, nullptr, r->N, r->stats, r->hist,
+                                    r->nbins, 1, r->mhr, r->parts, r->stream));
+            r->m_beta.push_back(r->beta);
+            r->m_lnZ.push_back(r->lnZ);
+            r->m_R.push_back(r->R_cur);
+        }
+        if (done < cap) host::observables(r->h_stats, r->R_cur, r->N, r->beta, r->lnZ, r->lnQ_last, &out[done]);
+        if (sweep_ms && done < cap) {
+            float ms = 0.0f;
+            if (sc->theta > 0) HIPCHK(hipEventElapsedTime(&ms, r->ev_t0, r->ev_t1));
+            sweep_ms[done] = ms;
+        }
+        ++done;
+        if (nsteps) *nsteps = done;
+    }
+    return PA_OK;
+}
+
 pa_status pa_alpha(pa_run* r, double beta_prime, double* alpha)
 {
     pa_status st = usable(r);
@@ -420,6 +550,8 @@ pa_status pa_free(pa_run* r)
 {
     if (!r) return PA_OK;
     if (r->ev_rnew) (void)hipEventDestroy(r->ev_rnew);
+    if (r->ev_t0) (void)hipEventDestroy(r->ev_t0);
+    if (r->ev_t1) (void)hipEventDestroy(r->ev_t1);
     if (r->pinned) (void)hipHostFree(r->pinned);
     delete r;
     return PA_OK;

@@ -234,6 +234,7 @@ __global__ __launch_bounds__(512) void b_sweep(const Item* __restrict__ items, c
     if (!post_resample(st, res[it.run], &buf, &n)) return;  // failed resampling: no sweep
     const RunDev& rd = runs[it.run];
     SweepArgs a;
+    a.n_dev = nullptr;
     a.spin = rd.spin[buf];
     a.E = rd.E[buf];
     a.M = rd.M[buf];

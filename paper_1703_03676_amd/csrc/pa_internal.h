@@ -44,14 +44,17 @@ struct SweepArgs {
     uint32_t t2h, t2l;      // threshold T_2 = t2h * 2^16 + t2l  (t2h <= 65536)
     uint32_t t4h, t4l;      // threshold T_4
     int32_t init;           // 1: draw the initial state instead of loading spins
+    const uint32_t* n_dev;  // if set: the population size is min(*n_dev, n_rep), read on the device
 };
 
 // Kernel launchers; each returns the launch status.
 hipError_t launch_sweep(int L, int layout, const SweepArgs& a, hipStream_t s);
 // Statistics of a population (after launch_stats_reset): histogram, range,
-// moment sums; parts holds ceil(n / kBlock) partials.
-hipError_t launch_stats(const int32_t* E, const int32_t* M, int32_t n, int32_t N, DevStats* st,
-                        uint32_t* hist, int32_t nbins, int record, DevMhr mhr, StatsPart* parts, hipStream_t s);
+// moment sums; parts holds ceil(n / kBlock) partials.  With n_dev the size is
+// min(*n_dev, n), read on the device.
+hipError_t launch_stats(const int32_t* E, const int32_t* M, int32_t n, const uint32_t* n_dev, int32_t N,
+                        DevStats* st, uint32_t* hist, int32_t nbins, int record, DevMhr mhr, StatsPart* parts,
+                        hipStream_t s);
 hipError_t launch_counts(const int32_t* E, int32_t n, int32_t N, int32_t bmin, int32_t nwin, const uint32_t* tbl,
                          uint32_t step, uint32_t key0, uint32_t key1, uint32_t* counts, uint32_t* bsum,
                          hipStream_t s);
@@ -64,6 +67,7 @@ hipError_t launch_copy(const uint8_t* src, const int32_t* Esrc, const int32_t* M
                        const uint32_t* n_new, int32_t cap, size_t rep_bytes, uint8_t* dst, int32_t* Edst,
                        int32_t* Mdst, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
+// Clears the range, the sums and the histogram (not r_new).
 hipError_t launch_stats_reset(DevStats* st, uint32_t* hist, int32_t nbins, hipStream_t s);
 
 constexpr int kBlock = 256;     // threads per block of the population kernels

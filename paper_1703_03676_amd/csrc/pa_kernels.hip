@@ -30,6 +30,7 @@ __global__ __launch_bounds__(sweep_block<L>()) void sweep_kernel(SweepArgs a)
     using Gm = Geo<L>;
     constexpr int WPB = sweep_block<L>() / 64;
     __shared__ uint32_t lds[Gm::lds_words(WPB) > 0 ? Gm::lds_words(WPB) : 1];
+    if (a.n_dev) a.n_rep = min(a.n_rep, (int32_t)*a.n_dev);
     sweep_waves<L, INT8>(a, (int)blockIdx.x * WPB, WPB, lds);
 }
 
@@ -37,16 +38,20 @@ __global__ __launch_bounds__(sweep_block<L>()) void sweep_kernel(SweepArgs a)
 // Population statistics (histogram, energy range, exact moment sums).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void stats_kernel(const int32_t* __restrict__ E, const int32_t* __restrict__ M,
-                                                       int32_t n, int32_t N, uint32_t* hist, int32_t nbins,
-                                                       int record, DevMhr mhr, StatsPart* parts)
+                                                       int32_t n, const uint32_t* n_dev, int32_t N, uint32_t* hist,
+                                                       int32_t nbins, int record, DevMhr mhr, StatsPart* parts)
 {
-    stats_block(E, M, n, N, (int32_t)(blockIdx.x * kBlock), hist, nbins, record != 0, mhr, &parts[blockIdx.x]);
+    if (n_dev) n = min(n, (int32_t)*n_dev);
+    const int32_t i0 = (int32_t)(blockIdx.x * kBlock);
+    if (i0 >= n) return;  // uniform per block
+    stats_block(E, M, n, N, i0, hist, nbins, record != 0, mhr, &parts[blockIdx.x]);
 }
 
-__global__ __launch_bounds__(kBlock) void stats_final_kernel(const StatsPart* __restrict__ parts, int32_t nparts,
-                                                             DevStats* st)
+__global__ __launch_bounds__(kBlock) void stats_final_kernel(const StatsPart* __restrict__ parts, int32_t n,
+                                                             const uint32_t* n_dev, DevStats* st)
 {
-    stats_final(parts, nparts, st);
+    if (n_dev) n = min(n, (int32_t)*n_dev);
+    stats_final(parts, (n + kBlock - 1) / kBlock, st);
 }
 
 __global__ void stats_reset_kernel(DevStats* st, uint32_t* hist, int32_t nbins)
@@ -55,8 +60,6 @@ __global__ void stats_reset_kernel(DevStats* st, uint32_t* hist, int32_t nbins)
     if (i == 0) {
         st->emin = 0x7FFFFFFF;
         st->emax = (int32_t)0x80000000;
-        st->r_new = 0;
-        st->pad = 0;
         st->sumE = st->sumE2 = st->sumAbsM = st->sumM2 = st->sumM4_lo = st->sumM4_hi = 0;
     }
     for (int b = i; b < nbins; b += (int)(gridDim.x * blockDim.x)) hist[b] = 0;
@@ -181,13 +184,15 @@ hipError_t launch_sweep(int L, int layout, const SweepArgs& a, hipStream_t s)
     }
 }
 
-hipError_t launch_stats(const int32_t* E, const int32_t* M, int32_t n, int32_t N, DevStats* st, uint32_t* hist,
-                        int32_t nbins, int record, DevMhr mhr, StatsPart* parts, hipStream_t s)
+hipError_t launch_stats(const int32_t* E, const int32_t* M, int32_t n, const uint32_t* n_dev, int32_t N,
+                        DevStats* st, uint32_t* hist, int32_t nbins, int record, DevMhr mhr, StatsPart* parts,
+                        hipStream_t s)
 {
     const int blocks = (n + kBlock - 1) / kBlock;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(stats_kernel, dim3(blocks), dim3(kBlock), 0, s, E, M, n, N, hist, nbins, record, mhr, parts);
-    hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(kBlock), 0, s, (const StatsPart*)parts, blocks, st);
+    hipLaunchKernelGGL(stats_kernel, dim3(blocks), dim3(kBlock), 0, s, E, M, n, n_dev, N, hist, nbins, record, mhr,
+                       parts);
+    hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(kBlock), 0, s, (const StatsPart*)parts, n, n_dev, st);
     return hipGetLastError();
 }
 hipError_t launch_stats_reset(DevStats* st, uint32_t* hist, int32_t nbins, hipStream_t s)

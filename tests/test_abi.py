@@ -73,6 +73,10 @@ def test_null_handle():
     assert lib.pa_resample(None, 0.1, None) == pa.PA_EINVAL
     assert lib.pa_observables(None, None) == pa.PA_EINVAL
     assert lib.pa_state(None, None) == pa.PA_EINVAL
+    sched = pa.make_schedule(beta_f=1.0, dbeta=0.01, theta=1)
+    n = ctypes.c_int32(7)
+    assert lib.pa_anneal(None, ctypes.byref(sched), 10, None, None, 0, ctypes.byref(n)) == pa.PA_EINVAL
+    assert n.value == 0
     assert lib.pa_free(None) == pa.PA_OK
     assert lib.pa_last_error(None) == b""
 

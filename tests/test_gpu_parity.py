@@ -176,6 +176,88 @@ def test_full_run_config1(layout, oracle_config1):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
+def test_anneal_config1(layout, oracle_config1):
+    """pa_anneal (one host round trip per step) against the oracle's step-by-
+    step config-1 run: every step's observables and the final population."""
+    print("case anneal config1 layout=%s" % layout, flush=True)
+    o, trace = oracle_config1
+    g = pa.Run(16, 1000, seed=1, layout=layout)
+    _same_obs(g.observables(), trace[0])
+    obs = g.anneal(beta_f=1.0, dbeta=0.01, theta=10, mode="fixed")
+    assert len(obs) == 100
+    for go, oo in zip(obs, trace[1:]):
+        _same_obs(go, oo)
+    _same_population(g, o)
+    st = g.state()
+    assert st["step"] == 100 and st["sweeps"] == 1000 and st["beta"] == 1.0 and st["lnZ"] == o.lnZ
+    assert g.anneal(beta_f=1.0, dbeta=0.01, theta=10) == []  # already at beta_f
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_anneal_adaptive_with_reweighting(layout):
+    """Adaptive pa_anneal with the multi-histogram record against the oracle
+    stepped by hand, then interrupted and resumed (max_steps)."""
+    print("case anneal adaptive layout=%s" % layout, flush=True)
+    L, R, theta = 16, 2000, 5
+    g = pa.Run(L, R, seed=9, layout=layout, mhr=True)
+    o = oracle.Run(L, R, seed=9)
+    o.init()
+    _same_obs(g.observables(), o.measure())
+    trace = []
+    while o.beta < 1.0:
+        b = o.adapt_beta(0.85, 1.0)
+        o.resample(b)
+        o.sweep(theta)
+        trace.append(o.measure())
+    first = g.anneal(beta_f=1.0, alpha_star=0.85, theta=theta, mode="adaptive", max_steps=3)
+    rest = g.anneal(beta_f=1.0, alpha_star=0.85, theta=theta, mode="adaptive")
+    assert len(first) == 3 and len(first) + len(rest) == len(trace)
+    for go, oo in zip(first + rest, trace):
+        _same_obs(go, oo)
+    _same_population(g, o)
+    betas = np.linspace(0.0, 1.2, 31)
+    for go, oo in zip(g.reweight(betas), o.reweight(betas)):
+        for k in ("e", "C", "abs_m", "m2", "m4", "betaF_per_N", "S_per_N"):
+            assert _close(go[k], oo[k], 1e-12), (k, go["beta"], go[k], oo[k])
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_anneal_capacity_refusal_keeps_state(layout):
+    """A step refused for capacity inside pa_anneal leaves the run at the last
+    completed step, usable, and equal to the oracle's."""
+    print("case anneal capacity layout=%s" % layout, flush=True)
+    refused = 0
+    for seed in range(1, 25):
+        g = pa.Run(16, 100, seed=seed, capacity=100, layout=layout)
+        o = oracle.Run(16, 100, seed=seed, capacity=100)
+        s = np.ones((3, 16, 16), np.int8)
+        # step 1 at beta 0.1: the fixed schedule's next step is beta_2 = 0.2
+        g.upload_population(s, step=1, beta=0.1)
+        o.set_population(s, step=1, beta=0.1)
+        try:
+            o.resample(0.2)
+            o.sweep(2)
+            ok = True
+        except OverflowError:
+            ok = False
+        if ok:
+            obs = g.anneal(beta_f=0.2, dbeta=0.1, theta=2)
+            assert len(obs) == 1
+            _same_obs(obs[0], o.measure())
+        else:
+            refused += 1
+            with pytest.raises(pa.CapacityError):
+                g.anneal(beta_f=0.2, dbeta=0.1, theta=2)
+            st = g.state()
+            assert st["step"] == 1 and st["R"] == 3 and st["sweeps"] == 0 and st["beta"] == 0.1
+            _same_obs(g.observables(), o.measure())
+            g.sweep(1)
+            o.sweep(1)
+        _same_population(g, o)
+    assert 0 < refused < 24
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 def test_config2_full_size_sampled(layout):
     """L=64, R=20000, theta=100: full-size init and resampling compared
     element by element; the 100 sweeps compared on sampled replicas swept by
