@@ -204,7 +204,7 @@ def run_plain_adaptive(pa, L, R_, theta, alpha, beta_f, seed, mhr=False):
     return run, flips, nsteps
 
 
-def workload_config3(pa, torch):
+def workload_l128_adaptive(pa, torch):
     """L=128, R=50000, theta=50, adaptive dbeta (alpha*=0.85), multi-histogram
     reweighting on a 1000-point beta grid; plain single-run form."""
     import numpy as np
@@ -219,7 +219,7 @@ def workload_config3(pa, torch):
     t_rw = time.perf_counter() - t1
     last = run.observables()
     return {
-        "workload": "config3: L=128, R=50000, theta=50, adaptive alpha*=0.85, beta 0->1, MHR on 1000 betas",
+        "workload": "L=128, R=50000, theta=50, adaptive alpha*=0.85, beta 0->1, MHR on 1000 betas",
         "flips_per_ns": flips / (t_run * 1e9), "run_wall_time_s": t_run, "temperature_steps": nsteps,
         "reweight_s": t_rw, "betaF_per_N_final": last["betaF_per_N"],
         "betaF_per_N_exact": _exact_betaF(L, 1.0),
@@ -227,27 +227,27 @@ def workload_config3(pa, torch):
     }
 
 
-CONFIG4_LR = [(L, R_) for L in (16, 32, 64, 128) for R_ in (5000, 20000)]
+BATCH64_LR = [(L, R_) for L in (16, 32, 64, 128) for R_ in (5000, 20000)]
 
 
-def _config4_runs(seed0):
+def _batch64_runs(seed0):
     return [dict(L=L, R=R_, seed=seed0 + 8 * k + s, layout="bits")
-            for k, (L, R_) in enumerate(CONFIG4_LR) for s in range(8)]
+            for k, (L, R_) in enumerate(BATCH64_LR) for s in range(8)]
 
 
 def _batch_errors(b, runs):
     return [abs(b.history(r)[-1]["betaF_per_N"] - _exact_betaF(sp["L"], 1.0)) for r, sp in enumerate(runs)]
 
 
-def workload_config4(pa, torch, sequential=True):
+def workload_batch64(pa, torch, sequential=True):
     """64 runs, (L, R) in {16,32,64,128} x {5000,20000}, theta=20, adaptive
     alpha*=0.85, beta 0->1: plain adaptive one run at a time, batched
     adaptive (one graph replay per step for all runs) and batched learned."""
     import numpy as np
     theta, alpha = 20, 0.85
-    out = {"workload": "config4: 64 runs, (L,R) in {16,32,64,128}x{5000,20000}, 8 seeds each, theta=20, "
+    out = {"workload": "64 runs, (L,R) in {16,32,64,128}x{5000,20000}, 8 seeds each, theta=20, "
                        "adaptive alpha*=0.85, beta 0->1"}
-    runs = _config4_runs(1)
+    runs = _batch64_runs(1)
     if sequential:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -282,7 +282,7 @@ def workload_config4(pa, torch, sequential=True):
     losses = m.train(xc, tc, batch=256, epochs=200, lr=3e-3, momentum=0.9, seed=1)
     t_train = time.perf_counter() - t0
     params, norm = m.params()
-    runs2 = _config4_runs(1001)
+    runs2 = _batch64_runs(1001)
     sched2 = dict(sched, mode="learned")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -299,17 +299,42 @@ def workload_config4(pa, torch, sequential=True):
                               "mean_abs_dbetaF_per_N": float(np.mean(_batch_errors(bl, runs2))),
                               "training_pairs": int(len(tt)), "train_s": t_train,
                               "train_loss_first_last": [float(losses[0]), float(losses[-1])]}
+    # shared schedule (Sec. 2.3, several runs): per (L, R) the first seed adapts,
+    # the other seven follow it, and the eight runs are combined by the
+    # free-energy-weighted average of Sec. 2.2
+    runs3 = _batch64_runs(2001)
+    sched3 = []
+    for k in range(len(BATCH64_LR)):
+        sched3.append(dict(sched, mode="adaptive"))
+        sched3.extend(dict(beta_f=1.0, theta=theta, mode="follow", leader=8 * k) for _ in range(7))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bs = pa.Batch(runs3, sched3)
+    bs.run()
+    t = time.perf_counter() - t0
+    steps = sum(len(bs.history(r)) - 1 for r in range(len(runs3)))
+    flips = sum(sp["L"] ** 2 * theta * o["R"] for r, sp in enumerate(runs3) for o in bs.history(r)[1:])
+    single, combined = [], []
+    for k, (L_, _) in enumerate(BATCH64_LR):
+        hs = [bs.history(8 * k + s) for s in range(8)]
+        ex = _exact_betaF(L_, 1.0)
+        single.extend(abs(h[-1]["betaF_per_N"] - ex) for h in hs)
+        combined.append(abs(pa.weighted_average(hs, L_ * L_)[-1]["betaF_per_N"] - ex))
+    out["batched_shared_schedule"] = {"s_per_run": t / len(runs3), "total_s": t, "flips_per_ns": flips / (t * 1e9),
+                                      "steps": steps, "mean_abs_dbetaF_per_N_single": float(np.mean(single)),
+                                      "mean_abs_dbetaF_per_N_weighted_8": float(np.mean(combined))}
+    bs.close()
     out["_model"] = (params, norm)
     return out
 
 
-def workload_config5(pa, torch):
+def workload_l256_learned(pa, torch):
     """L=256, R=100000, theta=20, beta 0->1: plain adaptive single run, then a
-    batched learned run with a proposer trained on config-4 adaptive pairs."""
-    c4 = workload_config4(pa, torch, sequential=False)
+    batched learned run with a proposer trained on the adaptive pairs of the 64-run batch."""
+    c4 = workload_batch64(pa, torch, sequential=False)
     params, norm = c4.pop("_model")
     L, R_, theta = 256, 100000, 20
-    out = {"workload": "config5: L=256, R=100000, theta=20, beta 0->1, adaptive vs learned (alpha*=0.85)"}
+    out = {"workload": "L=256, R=100000, theta=20, beta 0->1, adaptive vs learned (alpha*=0.85)"}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run, flips, nsteps = run_plain_adaptive(pa, L, R_, theta, 0.85, 1.0, seed=5)
@@ -341,12 +366,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--layouts", default="bits,int8")
-    ap.add_argument("--workload", default="config2", choices=["config2", "config3", "config4", "config5"],
-                    help="config2 (default) is the headline workload; the others print their own JSON line")
+    ap.add_argument("--workload", default="l64", choices=["l64", "l128_adaptive", "batch64", "l256_learned"],
+                    help="l64 (default) is the headline workload; the others print their own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(population annealing shards by replica; see DESIGN.md)", file=sys.stderr)
+              "(population annealing would shard by replica, one population share per GPU)", file=sys.stderr)
         return 2
 
     import torch
@@ -356,8 +381,9 @@ def main():
         from paper_1703_03676_amd import build as hip_build
         hip_build.build()
     torch.cuda.set_device(0)
-    if args.workload != "config2":
-        fn = {"config3": workload_config3, "config4": workload_config4, "config5": workload_config5}[args.workload]
+    if args.workload != "l64":
+        fn = {"l128_adaptive": workload_l128_adaptive, "batch64": workload_batch64,
+              "l256_learned": workload_l256_learned}[args.workload]
         res = fn(pa, torch)
         res.pop("_model", None)
         print(json.dumps(res), flush=True)

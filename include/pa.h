@@ -164,6 +164,22 @@ const char* pa_strerror(pa_status s);
 /* Text of the last error of this run ("" if none). */
 const char* pa_last_error(const pa_run* r);
 
+/* Weighted average of nruns independent runs of the same system and target
+ * population size, measured at the same nb inverse temperatures (Sec. 2.2,
+ * Eq. (weighted-average)).  obs[m * nb + i] is run m's measurement at the
+ * i-th temperature (as returned by pa_observables or pa_anneal); out[i]
+ * (nb entries, caller-owned) receives:
+ *   beta;  e, C, abs_m, m2, m4 weighted by w_m = exp(-beta F_m) / sum_m'
+ *   exp(-beta F_m'), with ln Z_m = -N * betaF_per_N of run m;
+ *   betaF_per_N of the pooled estimate of Z, -ln((1/M) sum_m Z_m) / N;
+ *   S_per_N = beta e + ln Z / N of the combination;  R = sum of the R_m;
+ *   lnQ and the integer sums 0.
+ * Host arithmetic only (FP64, runs summed in ascending order); no run handle
+ * and no device work.  PA_EINVAL: N < 1, nruns < 1, nb < 0, NULL arrays with
+ * nb > 0, or temperatures that differ between runs (out is then
+ * unspecified). */
+pa_status pa_weighted_average(int32_t N, int32_t nruns, int32_t nb, const pa_obs* obs, pa_obs* out);
+
 /* ---- Test hooks: step-wise comparison with a reference implementation. ---- */
 
 /* Copy the population to host memory: spins as int8 +-1, row-major,
@@ -201,7 +217,11 @@ pa_status pa_download_counts(pa_run* r, uint32_t* counts, int32_t* n);
 typedef enum {
     PA_STEP_FIXED = 0,     /* beta_i = i * dbeta, last step clamped to beta_f (Sec. 2.1) */
     PA_STEP_ADAPTIVE = 1,  /* histogram-overlap bisection to alpha_star (Sec. 2.3) */
-    PA_STEP_LEARNED = 2    /* learned proposal accepted by the exact overlap test, else bisection */
+    PA_STEP_LEARNED = 2,   /* learned proposal accepted by the exact overlap test, else bisection */
+    PA_STEP_FOLLOW = 3     /* take the leader run's beta_{i} at every step: the schedule of the
+                              first run is reused by the others (Sec. 2.3, several runs), which
+                              puts independent runs on common temperatures for
+                              pa_weighted_average (Sec. 2.2) */
 } pa_step_mode;
 
 typedef struct {
@@ -211,6 +231,10 @@ typedef struct {
     double alpha_tol;    /* learned mode: accept a proposal if |alpha - alpha_star| <= alpha_tol */
     int32_t theta;       /* sweeps per temperature step (>= 0) */
     int32_t mode;        /* pa_step_mode */
+    int32_t leader;      /* PA_STEP_FOLLOW: index of the leading run in the batch, whose own
+                            mode is not PA_STEP_FOLLOW; beta_f is then the leader's.  A
+                            follower stops with PA_ESTATE once its leader has stopped on an
+                            error.  Ignored in the other modes. */
 } pa_schedule;
 
 /* Single run: temperature steps of Sec. 2.1 from the current state until

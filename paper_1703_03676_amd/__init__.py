@@ -70,11 +70,13 @@ class StateInfo(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("beta_f", ctypes.c_double), ("dbeta", ctypes.c_double), ("alpha_star", ctypes.c_double),
-                ("alpha_tol", ctypes.c_double), ("theta", ctypes.c_int32), ("mode", ctypes.c_int32)]
+                ("alpha_tol", ctypes.c_double), ("theta", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("leader", ctypes.c_int32)]
 
 
-PA_STEP_FIXED, PA_STEP_ADAPTIVE, PA_STEP_LEARNED = 0, 1, 2
-STEP_MODES = {"fixed": PA_STEP_FIXED, "adaptive": PA_STEP_ADAPTIVE, "learned": PA_STEP_LEARNED}
+PA_STEP_FIXED, PA_STEP_ADAPTIVE, PA_STEP_LEARNED, PA_STEP_FOLLOW = 0, 1, 2, 3
+STEP_MODES = {"fixed": PA_STEP_FIXED, "adaptive": PA_STEP_ADAPTIVE, "learned": PA_STEP_LEARNED,
+              "follow": PA_STEP_FOLLOW}
 
 
 # Every symbol declared in include/pa.h, with its ctypes signature.
@@ -84,6 +86,7 @@ SIGNATURES = {
     "pa_workspace_bytes": (ctypes.c_size_t, [_P(Params)]),
     "pa_init": (ctypes.c_int, [_P(Params), _vp, ctypes.c_size_t, _vp, _P(_vp)]),
     "pa_sweep": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pa_weighted_average": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _vp, _vp]),
     "pa_anneal": (ctypes.c_int, [_vp, _P(Schedule), ctypes.c_int32, _vp, _vp, ctypes.c_int32, _P(ctypes.c_int32)]),
     "pa_resample": (ctypes.c_int, [_vp, ctypes.c_double, _P(ResampleInfo)]),
     "pa_adapt_beta": (ctypes.c_int, [_vp, ctypes.c_double, ctypes.c_double, _P(ctypes.c_double), _P(ctypes.c_double)]),
@@ -137,8 +140,7 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise RuntimeError("libpa.so is not built (run __graft_entry__.build() or "
-                               "python paper_1703_03676_amd/build.py)")
+            raise RuntimeError("libpa.so is not built (run python paper_1703_03676_amd/build.py)")
         import torch  # noqa: F401  (binds the HIP runtime before libpa is loaded)
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
@@ -179,6 +181,30 @@ def workspace_bytes(params):
 
 def _ptr(a):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _obs_struct(d):
+    o = Obs()
+    for name, _ in Obs._fields_:
+        if name in ("sumM4_lo", "sumM4_hi"):
+            continue
+        if name in d:
+            setattr(o, name, d[name])
+    m4 = int(d.get("sumM4", 0))
+    o.sumM4_lo, o.sumM4_hi = m4 & ((1 << 64) - 1), m4 >> 64
+    return o
+
+
+def weighted_average(runs, N):
+    """Free-energy-weighted average of independent runs (lists of observable
+    dicts at the same temperatures); N = L * L.  Host arithmetic in libpa."""
+    nruns, nb = len(runs), len(runs[0]) if runs else 0
+    if any(len(r) != nb for r in runs):
+        raise PaError(PA_EINVAL, "runs measured at different numbers of temperatures")
+    flat = (Obs * (nruns * nb))(*[_obs_struct(o) for r in runs for o in r])
+    out = (Obs * max(nb, 1))()
+    _check(lib().pa_weighted_average(int(N), nruns, nb, ctypes.cast(flat, _vp), ctypes.cast(out, _vp)))
+    return [o.as_dict() for o in out[:nb]]
 
 
 class Run:
@@ -302,10 +328,10 @@ class Run:
         return buf[: n.value].copy()
 
 
-def make_schedule(beta_f=1.0, dbeta=0.0, alpha_star=0.0, alpha_tol=0.0, theta=1, mode="fixed"):
+def make_schedule(beta_f=1.0, dbeta=0.0, alpha_star=0.0, alpha_tol=0.0, theta=1, mode="fixed", leader=0):
     return Schedule(beta_f=float(beta_f), dbeta=float(dbeta), alpha_star=float(alpha_star),
                     alpha_tol=float(alpha_tol), theta=int(theta),
-                    mode=STEP_MODES[mode] if isinstance(mode, str) else int(mode))
+                    mode=STEP_MODES[mode] if isinstance(mode, str) else int(mode), leader=int(leader))
 
 
 class Batch:

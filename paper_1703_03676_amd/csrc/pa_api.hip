@@ -535,6 +535,12 @@ pa_status pa_reweight(pa_run* r, const double* betas, int32_t nb, pa_obs* out)
     return PA_OK;
 }
 
+pa_status pa_weighted_average(int32_t N, int32_t nruns, int32_t nb, const pa_obs* obs, pa_obs* out)
+{
+    if (N < 1 || nruns < 1 || nb < 0 || (nb > 0 && (!obs || !out))) return PA_EINVAL;
+    return host::weighted_average(N, nruns, nb, obs, out) ? PA_OK : PA_EINVAL;
+}
+
 pa_status pa_state(const pa_run* r, pa_state_info* out)
 {
     if (!r || !out) return PA_EINVAL;

@@ -395,6 +395,7 @@ bool valid_schedule(const pa_schedule& s)
     case PA_STEP_FIXED: return s.dbeta > 0.0 && std::isfinite(s.dbeta);
     case PA_STEP_ADAPTIVE: return s.alpha_star > 0.0 && s.alpha_star < 1.0;
     case PA_STEP_LEARNED: return s.alpha_star > 0.0 && s.alpha_star < 1.0 && s.alpha_tol >= 0.0;
+    case PA_STEP_FOLLOW: return true;  // the leader is checked against the whole batch
     default: return false;
     }
 }
@@ -848,8 +849,14 @@ static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int
                             size_t bytes, void* hip_stream, pa_batch** out)
 {
     if (!runs || !sched || nruns < 1 || !d_workspace || ((uintptr_t)d_workspace) % kAlign) return PA_EINVAL;
-    for (int r = 0; r < nruns; ++r)
-        if (!valid_schedule(sched[r])) return PA_EINVAL;
+    for (int r = 0; r < nruns; ++r) {
+        if (sched[r].mode == PA_STEP_FOLLOW) {
+            const int l = sched[r].leader;
+            if (l < 0 || l >= nruns || l == r || sched[l].mode == PA_STEP_FOLLOW || sched[r].theta < 0) return PA_EINVAL;
+        } else if (!valid_schedule(sched[r])) {
+            return PA_EINVAL;
+        }
+    }
     BatchLayout bl;
     if (!make_batch_layout(runs, nruns, &bl)) return PA_EINVAL;
     if (bytes < bl.total) return PA_ENOMEM;
@@ -882,6 +889,7 @@ static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int
         h.p = runs[r];
         h.p.capacity = rl.capacity;
         h.sched = sched[r];
+        if (h.sched.mode == PA_STEP_FOLLOW) h.sched.beta_f = sched[h.sched.leader].beta_f;
         RunDev& d = b->rundev[(size_t)r];
         std::memset(&d, 0, sizeof(d));
         for (int k = 0; k < 2; ++k) {
@@ -1016,13 +1024,25 @@ pa_status pa_batch_step(pa_batch* b, int32_t* n_active)
     b->pool->parallel_for(b->nruns, [&](int r) {
         RunHost& h = b->runs[(size_t)r];
         h.stepping = false;
-        if (h.finished || h.status != PA_OK) return;
+        if (h.finished || h.status != PA_OK || h.sched.mode == PA_STEP_FOLLOW) return;
         const host::Hist hw = host::hist_window(h.h_hist, h.h_stats, h.p.L * h.p.L);
         double bn = 0.0;
         if (!choose_beta(h, hw, b->model_set, &bn)) return;
         h.beta_next = bn;
         h.stepping = true;
     });
+    // followers take their leader's temperature of this step
+    for (int r = 0; r < b->nruns; ++r) {
+        RunHost& h = b->runs[(size_t)r];
+        if (h.sched.mode != PA_STEP_FOLLOW || h.finished || h.status != PA_OK) continue;
+        const RunHost& l = b->runs[(size_t)h.sched.leader];
+        if (l.stepping && l.step == h.step) {
+            h.beta_next = l.beta_next;
+            h.stepping = true;
+        } else if (l.status != PA_OK || l.step != h.step) {
+            h.status = PA_ESTATE;  // the leader has stopped (or fell behind on an error)
+        }
+    }
     // phase 2: pack the table windows
     std::vector<uint32_t> toff((size_t)b->nruns, 0u);
     uint32_t o = 0;

@@ -221,6 +221,51 @@ inline void reweight(int N_, const uint64_t* H, const uint64_t* SA, const uint64
     }
 }
 
+// Weighted average of nruns runs measured at the same nb temperatures (Sec.
+// 2.2, Eq. (weighted-average)); obs[m * nb + i].  Weights w_m =
+// exp(ln Z_m) / sum exp(ln Z_m') with ln Z_m = -N (beta F/N)_m, taken relative
+// to the largest ln Z_m; the combined free energy is that of the pooled
+// estimate ln((1/M) sum_m Z_m).  Sums run over m in ascending order.  Returns
+// false if the runs' temperatures differ.
+inline bool weighted_average(int N_, int nruns, int nb, const pa_obs* obs, pa_obs* out)
+{
+    const double N = (double)N_;
+    std::vector<double> lnZ((size_t)nruns), z((size_t)nruns);
+    for (int i = 0; i < nb; ++i) {
+        const double beta = obs[i].beta;
+        double top = -INFINITY;
+        for (int m = 0; m < nruns; ++m) {
+            const pa_obs& o = obs[(size_t)m * nb + i];
+            if (o.beta != beta) return false;
+            lnZ[(size_t)m] = -N * o.betaF_per_N;
+            if (lnZ[(size_t)m] > top) top = lnZ[(size_t)m];
+        }
+        double S = 0.0;
+        for (int m = 0; m < nruns; ++m) {
+            z[(size_t)m] = std::exp(lnZ[(size_t)m] - top);
+            S += z[(size_t)m];
+        }
+        pa_obs r;
+        std::memset(&r, 0, sizeof(r));
+        r.beta = beta;
+        for (int m = 0; m < nruns; ++m) {
+            const pa_obs& o = obs[(size_t)m * nb + i];
+            const double w = z[(size_t)m] / S;
+            r.e += w * o.e;
+            r.C += w * o.C;
+            r.abs_m += w * o.abs_m;
+            r.m2 += w * o.m2;
+            r.m4 += w * o.m4;
+            r.R += o.R;
+        }
+        const double lnZc = top + std::log(S) - std::log((double)nruns);
+        r.betaF_per_N = -lnZc / N;
+        r.S_per_N = beta * r.e + lnZc / N;
+        out[i] = r;
+    }
+    return true;
+}
+
 // Bit store (colour 0 words then colour 1 words; bit q & 31 of word q >> 5 is
 // within-colour site q = (y L + x) >> 1; set = spin -1) <-> int8 row-major.
 inline void bits_to_int8(const uint32_t* words, int L, size_t n, int8_t* spins)

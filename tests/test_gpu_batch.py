@@ -151,3 +151,49 @@ def test_batch_argument_errors():
         pa.Batch([dict(L=16, R=10, seed=1)], dict(beta_f=1.0, dbeta=0.0, theta=1, mode="fixed"))
     with pytest.raises(pa.PaError):
         pa.Batch([dict(L=16, R=10, seed=1)], dict(beta_f=1.0, alpha_star=1.5, theta=1, mode="adaptive"))
+
+
+def test_shared_schedule_and_weighted_average():
+    """Run 0 adapts its temperatures; runs 1-4 (other seeds, both stores) follow
+    it step for step.  Every follower equals an oracle run replaying the
+    leader's temperatures, and the library's weighted average of the five runs
+    equals the oracle's (Sec. 2.2)."""
+    print("case shared schedule", flush=True)
+    L, R, theta = 16, 400, 3
+    runs = [dict(L=L, R=R, seed=100 + k, layout=("bits", "int8")[k % 2]) for k in range(5)]
+    scheds = [dict(beta_f=1.0, alpha_star=0.85, theta=theta, mode="adaptive")] + \
+        [dict(beta_f=5.0, theta=theta, mode="follow", leader=0) for _ in range(4)]
+    b = pa.Batch(runs, scheds)
+    b.run()
+    hists = [b.history(r) for r in range(5)]
+    betas = [o["beta"] for o in hists[0]]
+    assert betas[-1] == 1.0 and len(betas) > 5
+    for r in range(5):
+        assert b.status(r) == pa.PA_OK
+        assert [o["beta"] for o in hists[r]] == betas
+    for r in range(1, 5):
+        o = oracle.Run(L, R, seed=100 + r)
+        o.init()
+        trace = [o.measure()]
+        for beta in betas[1:]:
+            o.resample(beta)
+            o.sweep(theta)
+            trace.append(o.measure())
+        for go, oo in zip(hists[r], trace):
+            _same_obs(go, oo)
+    from oracle import weighted
+    got = pa.weighted_average(hists, L * L)
+    want = weighted.weighted_average(hists, L * L)
+    for g, w in zip(got, want):
+        for k in ("e", "C", "abs_m", "m2", "m4", "betaF_per_N", "S_per_N"):
+            assert _close(g[k], w[k]), k
+
+
+def test_follow_schedule_validation():
+    runs = [dict(L=16, R=50, seed=1), dict(L=16, R=50, seed=2)]
+    with pytest.raises(pa.PaError):
+        pa.Batch(runs, [dict(beta_f=1.0, dbeta=0.1, mode="fixed"), dict(mode="follow", leader=1)])
+    with pytest.raises(pa.PaError):
+        pa.Batch(runs, [dict(mode="follow", leader=1), dict(mode="follow", leader=0)])
+    with pytest.raises(pa.PaError):
+        pa.Batch(runs, [dict(beta_f=1.0, dbeta=0.1, mode="fixed"), dict(mode="follow", leader=7)])

@@ -146,7 +146,7 @@ def test_statistics_windows_and_multi_histogram(L, R, kind, layout):
             assert _close(go[k], oo[k], 1e-12), (k, go["beta"], go[k], oo[k])
 
 
-def _config1_trace(run, nsteps, theta, dbeta, measure):
+def _l16_trace(run, nsteps, theta, dbeta, measure):
     trace = [measure()]
     for i in range(1, nsteps + 1):
         run.resample(i * dbeta)
@@ -156,31 +156,31 @@ def _config1_trace(run, nsteps, theta, dbeta, measure):
 
 
 @pytest.fixture(scope="module")
-def oracle_config1():
+def oracle_l16_run():
     """L=16, R=1000, theta=10, dbeta=0.01, beta 0 -> 1 (100 steps), seed 1."""
     o = oracle.Run(16, 1000, seed=1)
     o.init()
-    trace = _config1_trace(o, 100, 10, 0.01, o.measure)
+    trace = _l16_trace(o, 100, 10, 0.01, o.measure)
     return o, trace
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_full_run_config1(layout, oracle_config1):
-    print("case config1 layout=%s" % layout, flush=True)
-    o, otrace = oracle_config1
+def test_full_run_l16_r1000(layout, oracle_l16_run):
+    print("case l16 run layout=%s" % layout, flush=True)
+    o, otrace = oracle_l16_run
     g = pa.Run(16, 1000, seed=1, layout=layout)
-    gtrace = _config1_trace(g, 100, 10, 0.01, g.observables)
+    gtrace = _l16_trace(g, 100, 10, 0.01, g.observables)
     for go, oo in zip(gtrace, otrace):
         _same_obs(go, oo)
     _same_population(g, o)
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_anneal_config1(layout, oracle_config1):
+def test_anneal_l16_run(layout, oracle_l16_run):
     """pa_anneal (one host round trip per step) against the oracle's step-by-
-    step config-1 run: every step's observables and the final population."""
-    print("case anneal config1 layout=%s" % layout, flush=True)
-    o, trace = oracle_config1
+    step L=16, R=1000 run: every step's observables and the final population."""
+    print("case anneal l16 run layout=%s" % layout, flush=True)
+    o, trace = oracle_l16_run
     g = pa.Run(16, 1000, seed=1, layout=layout)
     _same_obs(g.observables(), trace[0])
     obs = g.anneal(beta_f=1.0, dbeta=0.01, theta=10, mode="fixed")
@@ -258,12 +258,12 @@ def test_anneal_capacity_refusal_keeps_state(layout):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_config2_full_size_sampled(layout):
+def test_l64_r20000_full_size_sampled(layout):
     """L=64, R=20000, theta=100: full-size init and resampling compared
     element by element; the 100 sweeps compared on sampled replicas swept by
     the oracle alone at their slots; invariants checked on every replica."""
     L, R, theta = 64, 20000, 100
-    print("case config2 layout=%s" % layout, flush=True)
+    print("case l64 r20000 layout=%s" % layout, flush=True)
     g = pa.Run(L, R, seed=1, layout=layout)
     o = oracle.Run(L, R, seed=1)
     o.init()
