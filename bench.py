@@ -366,6 +366,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--layouts", default="bits,int8")
+    ap.add_argument("--no-step-calls", action="store_true",
+                    help="skip the comparison runs driven one C-ABI call at a time")
     ap.add_argument("--workload", default="l64", choices=["l64", "l128_adaptive", "batch64", "l256_learned"],
                     help="l64 (default) is the headline workload; the others print their own JSON line")
     args = ap.parse_args()
@@ -390,7 +392,7 @@ def main():
         return 0
     layouts = args.layouts.split(",")
     res = {lay: time_layout(pa, torch, lay, args.steps, args.warmup) for lay in layouts}
-    steps_cmp = time_step_calls(pa, torch, layouts[0], 2)
+    steps_cmp = None if args.no_step_calls else time_step_calls(pa, torch, layouts[0], 2)
     head = res[layouts[0]]
     achieved = head["sweep_flips_avg"] * SLOTS_PER_FLIP / (head["sweep_ms_avg"] * 1e-3)
     out = {
@@ -428,8 +430,9 @@ def main():
         },
         "layouts": {lay: {k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
                     for lay, r in res.items()},
-        "step_calls_%s" % layouts[0]: {k: round(v, 4) for k, v in steps_cmp.items()},
     }
+    if steps_cmp:
+        out["step_calls_%s" % layouts[0]] = {k: round(v, 4) for k, v in steps_cmp.items()}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)
