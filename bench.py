@@ -359,6 +359,33 @@ def workload_l256_learned(pa, torch):
     return out
 
 
+def workload_resample_l256(pa, torch):
+    """Resampling alone at L=256, R=100000 (both stores): 20 steps of dbeta =
+    0.0005 from the initial population, no sweeps.  The replica copy moves
+    2 x R x (N/8 or N) bytes per step and is the HBM-bound kernel of the path;
+    the time per pa_resample call (counts, scan, scatter, copy, one host
+    round trip) is reported with the bytes the copy moves."""
+    L_, R_ = 256, 100000
+    out = {"workload": "resampling only, L=256, R=100000, 20 steps of dbeta=0.0005, no sweeps"}
+    for layout in ("bits", "int8"):
+        run = pa.Run(L_, R_, seed=3, layout=layout)
+        run.resample(0.0005)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        copied = 0
+        for k in range(2, 22):
+            info = run.resample(0.0005 * k)
+            copied += info["R_new"]
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        rep = L_ * L_ // 8 if layout == "bits" else L_ * L_
+        moved = 2 * copied * rep
+        out[layout] = {"ms_per_resample": 1e3 * t / 20, "copy_bytes_per_step": moved / 20,
+                       "GB_per_s_whole_call": moved / t / 1e9}
+        run.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -368,7 +395,8 @@ def main():
     ap.add_argument("--layouts", default="bits,int8")
     ap.add_argument("--no-step-calls", action="store_true",
                     help="skip the comparison runs driven one C-ABI call at a time")
-    ap.add_argument("--workload", default="l64", choices=["l64", "l128_adaptive", "batch64", "l256_learned"],
+    ap.add_argument("--workload", default="l64",
+                    choices=["l64", "l128_adaptive", "batch64", "l256_learned", "resample_l256"],
                     help="l64 (default) is the headline workload; the others print their own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -385,7 +413,7 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "l64":
         fn = {"l128_adaptive": workload_l128_adaptive, "batch64": workload_batch64,
-              "l256_learned": workload_l256_learned}[args.workload]
+              "l256_learned": workload_l256_learned, "resample_l256": workload_resample_l256}[args.workload]
         res = fn(pa, torch)
         res.pop("_model", None)
         print(json.dumps(res), flush=True)

@@ -1262,15 +1262,54 @@ namespace {
 // spare half of each run's ping-pong store: the spare buffers are overwritten
 // by the first resampling, so tuning leaves no trace in the runs.  The timed
 // launches draw a fresh state and do a few sweeps at beta = 0.44.
+// Waves per block chosen by autotune, kept for the life of the process per
+// (device architecture, L, store, total replicas of the group rounded up to a
+// power of two): later batches of the same shape skip the timed search.
+struct TuneKey {
+    std::string arch;
+    int L, layout;
+    int64_t reps;
+    bool operator<(const TuneKey& o) const
+    {
+        if (arch != o.arch) return arch < o.arch;
+        if (L != o.L) return L < o.L;
+        if (layout != o.layout) return layout < o.layout;
+        return reps < o.reps;
+    }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune_cache;
+
 pa_status autotune(pa_batch* b)
 {
     const int cands[] = {1, 2, 4, 8};
     StepDev* sd = host_steps(b);
+    int dev = 0;
+    BCHK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    BCHK(hipGetDeviceProperties(&prop, dev));
+    const std::string arch = prop.gcnArchName;
     hipEvent_t e0, e1;
     BCHK(hipEventCreate(&e0));
     BCHK(hipEventCreate(&e1));
     std::vector<Item> it;
     for (Group& g : b->groups) {
+        int64_t reps = 0;
+        for (int r = 0; r < b->nruns; ++r) {
+            const RunHost& h = b->runs[(size_t)r];
+            if (h.p.L == g.L && h.p.layout == g.layout) reps += h.p.R;
+        }
+        int64_t bucket = 1;
+        while (bucket < reps) bucket <<= 1;
+        const TuneKey key{arch, g.L, g.layout, bucket};
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            const auto f = g_tune_cache.find(key);
+            if (f != g_tune_cache.end()) {
+                g.wpb = f->second;
+                continue;
+            }
+        }
         for (int r = 0; r < b->nruns; ++r) {
             StepDev& d = sd[r];
             std::memset(&d, 0, sizeof(d));
@@ -1310,6 +1349,8 @@ pa_status autotune(pa_batch* b)
             }
         }
         g.wpb = best_w;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best_w;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -137,7 +137,11 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(const uint32_t* __restr
 
 // Replica copy child <- parent[child] for child < min(*n_new, cap); the size
 // of the new population is read on the device, so the copy can be queued
-// before the host has seen it.
+// before the host has seen it.  A team of T threads (T divides the block, at
+// most the 16-byte chunks of a replica) moves one child at a time: one parent
+// index per team, contiguous coalesced 16-byte chunks, no per-chunk index
+// arithmetic; four chunks per thread are in flight.  Plain HBM streaming.
+template <int T>
 __global__ __launch_bounds__(kBlock) void copy_kernel(const uint4* __restrict__ src, const int32_t* __restrict__ Es,
                                                       const int32_t* __restrict__ Ms,
                                                       const uint32_t* __restrict__ parent,
@@ -145,15 +149,31 @@ __global__ __launch_bounds__(kBlock) void copy_kernel(const uint4* __restrict__ 
                                                       uint32_t chunks, uint4* __restrict__ dst,
                                                       int32_t* __restrict__ Ed, int32_t* __restrict__ Md)
 {
+    constexpr int TEAMS = kBlock / T;
     const uint32_t nn = min(*n_new, cap);
-    const size_t total = (size_t)nn * chunks;
-    for (size_t i = blockIdx.x * (size_t)kBlock + threadIdx.x; i < total; i += (size_t)gridDim.x * kBlock) {
-        const uint32_t child = (uint32_t)(i / chunks), ch = (uint32_t)(i % chunks);
+    const int t = (int)(threadIdx.x % T), team = (int)(threadIdx.x / T);
+    for (uint32_t child = blockIdx.x * TEAMS + (uint32_t)team; child < nn; child += gridDim.x * TEAMS) {
         const uint32_t p = parent[child];
-        dst[i] = src[(size_t)p * chunks + ch];
-        if (ch == 0) {
-            Ed[child] = Es[p];
-            Md[child] = Ms[p];
+        // E and M are loaded first so that their latency overlaps the spins
+        int32_t e = 0, m = 0;
+        if (t == 0) {
+            e = Es[p];
+            m = Ms[p];
+        }
+        const uint4* s = src + (size_t)p * chunks;
+        uint4* d = dst + (size_t)child * chunks;
+        uint32_t c = (uint32_t)t;
+        for (; c + 3u * T < chunks; c += 4u * T) {
+            const uint4 v0 = s[c], v1 = s[c + T], v2 = s[c + 2 * T], v3 = s[c + 3 * T];
+            d[c] = v0;
+            d[c + T] = v1;
+            d[c + 2 * T] = v2;
+            d[c + 3 * T] = v3;
+        }
+        for (; c < chunks; c += T) d[c] = s[c];
+        if (t == 0) {
+            Ed[child] = e;
+            Md[child] = m;
         }
     }
 }
@@ -239,12 +259,23 @@ hipError_t launch_copy(const uint8_t* src, const int32_t* Esrc, const int32_t* M
                        const uint32_t* n_new, int32_t cap, size_t rep_bytes, uint8_t* dst, int32_t* Edst,
                        int32_t* Mdst, hipStream_t s)
 {
-    const uint32_t chunks = (uint32_t)(rep_bytes / 16);
-    const size_t total = (size_t)cap * chunks;
-    if (total == 0) return hipSuccess;
-    const size_t blocks = std::min<size_t>((total + kBlock - 1) / kBlock, 8192);
-    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, s, reinterpret_cast<const uint4*>(src),
-                       Esrc, Msrc, parent, n_new, (uint32_t)cap, chunks, reinterpret_cast<uint4*>(dst), Edst, Mdst);
+    const uint32_t chunks = (uint32_t)(rep_bytes / 16);  // 32 (L = 64, bits) ... 4096 (L = 256, int8)
+    if (cap <= 0 || chunks == 0) return hipSuccess;
+    const uint4* sp = reinterpret_cast<const uint4*>(src);
+    uint4* dp = reinterpret_cast<uint4*>(dst);
+    // one child per team; enough blocks to cover the population up to 8192
+    // blocks (32 per CU), the rest by the grid-stride loop
+    auto grid = [&](int teams) { return (unsigned)std::min<int64_t>(((int64_t)cap + teams - 1) / teams, 8192); };
+    if (chunks >= 256) {
+        hipLaunchKernelGGL((copy_kernel<256>), dim3(grid(1)), dim3(kBlock), 0, s, sp, Esrc, Msrc, parent, n_new,
+                           (uint32_t)cap, chunks, dp, Edst, Mdst);
+    } else if (chunks >= 64) {
+        hipLaunchKernelGGL((copy_kernel<64>), dim3(grid(4)), dim3(kBlock), 0, s, sp, Esrc, Msrc, parent, n_new,
+                           (uint32_t)cap, chunks, dp, Edst, Mdst);
+    } else {
+        hipLaunchKernelGGL((copy_kernel<16>), dim3(grid(16)), dim3(kBlock), 0, s, sp, Esrc, Msrc, parent, n_new,
+                           (uint32_t)cap, chunks, dp, Edst, Mdst);
+    }
     return hipGetLastError();
 }
 
