@@ -37,6 +37,7 @@ L, R, THETA, DBETA, NSTEPS = 64, 20000, 100, 0.005, 200
 #   2 three-input xors) = 40 slots each, plus about 32 slots of bit-sliced
 #   neighbour, class and comparison logic: (2*40 + 32) / 32 = 3.5 slots.
 VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+HBM_PEAK = 8.0e12  # bytes/s
 SLOTS_PER_FLIP = 3.5
 PROFILE = os.path.join(ROOT, "profiles", "sweep_kernel_L64_R20000_theta100.md")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_1703_03676_amd", "csrc", f) for f in ("pa_device.h", "pa_kernels.hip")]
@@ -423,6 +424,7 @@ def main():
     steps_cmp = None if args.no_step_calls else time_step_calls(pa, torch, layouts[0], 2)
     head = res[layouts[0]]
     achieved = head["sweep_flips_avg"] * SLOTS_PER_FLIP / (head["sweep_ms_avg"] * 1e-3)
+    traffic = measured_traffic()
     out = {
         "metric": "attempted spin flips/ns + PA run wall-time (L=64,R=20000) on 1 MI355X vs HBM roofline",
         "value": round(head["flips_per_ns"], 3),
@@ -451,7 +453,8 @@ def main():
             "peak": round(VALU_PEAK_SLOTS / 1e12, 2),
             "unit": "Tops/s (VALU lane-slots, %.1f per attempted flip)" % SLOTS_PER_FLIP,
             "frac": round(achieved / VALU_PEAK_SLOTS, 4),
-            "traffic": measured_traffic(),
+            "traffic": traffic,
+            "hbm_frac": (round(traffic / (head["sweep_ms_avg"] * 1e-3) / HBM_PEAK, 5) if traffic else None),
             "kernel_ms_avg": round(head["sweep_ms_avg"], 4),
             "flips_per_launch": head["sweep_flips_avg"],
             "kernel_share_of_run": round(head["sweep_share"], 4),
