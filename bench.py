@@ -40,7 +40,8 @@ VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 HBM_PEAK = 8.0e12  # bytes/s
 SLOTS_PER_FLIP = 3.5
 PROFILE = os.path.join(ROOT, "profiles", "sweep_kernel_L64_R20000_theta100.md")
-KERNEL_SRCS = [os.path.join(ROOT, "paper_1703_03676_amd", "csrc", f) for f in ("pa_device.h", "pa_kernels.hip")]
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1703_03676_amd", "csrc", f)
+               for f in ("pa_internal.h", "pa_device.h", "pa_sweep.hip")]
 
 
 def kernel_source_hash():

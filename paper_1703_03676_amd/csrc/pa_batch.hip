@@ -35,6 +35,7 @@
 
 #include "pa.h"
 #include "pa_device.h"
+#include "pa_reduce.h"
 #include "pa_host.h"
 #include "pa_mlp_dev.h"
 

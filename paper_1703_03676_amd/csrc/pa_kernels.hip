@@ -1,38 +1,19 @@
-// Device kernels of the population-annealing hot path for gfx950 (CDNA4).
+// Population kernels of the single-run path for gfx950 (CDNA4); the sweep
+// kernel is in pa_sweep.hip.
 //
-//   sweep_kernel   checkerboard Metropolis sweeps (Sec. 3 spin updates), also
-//                  draws the initial state (Sec. 2.1 step 1) and recounts E, M
 //   stats_kernel   energy histogram, energy range and exact moment sums
 //                  (inputs of Eq. (Q), Eq. (observables), multi-histogram)
 //   counts_kernel  integer copy counts, Eq. (resampling factors)
 //   scan / scatter prefix sum of the counts -> parent index of every child
 //   copy_kernel    replica copy into the other half of the ping-pong store
 //
-// Spin representation inside the sweep: each colour of a replica is a set of
-// 32-site words (canonical within-colour index q = (y L + x) >> 1, bit q & 31
-// of word q >> 5; bit set = spin -1).  A wave owns whole replicas and keeps
-// them in VGPRs for all requested sweeps; vertical neighbours cross lanes by
-// shuffle, horizontal neighbours are funnel shifts.  The Metropolis decision
-// for all 32 sites of a word is bit-sliced: the uniform of each site is
-// compared to the integer threshold one bit plane at a time (16 planes from
-// four Philox blocks, high bit first), and the planes stop as soon as no site
-// in the wave is still undecided.
 #include "pa_device.h"
+#include "pa_reduce.h"
 
 namespace pa {
 namespace {
 
 using namespace pa::dev;
-
-template <int L, bool INT8>
-__global__ __launch_bounds__(sweep_block<L>()) void sweep_kernel(SweepArgs a)
-{
-    using Gm = Geo<L>;
-    constexpr int WPB = sweep_block<L>() / 64;
-    __shared__ uint32_t lds[Gm::lds_words(WPB) > 0 ? Gm::lds_words(WPB) : 1];
-    if (a.n_dev) a.n_rep = min(a.n_rep, (int32_t)*a.n_dev);
-    sweep_waves<L, INT8>(a, (int)blockIdx.x * WPB, WPB, lds);
-}
 
 // ---------------------------------------------------------------------------
 // Population statistics (histogram, energy range, exact moment sums).
@@ -178,31 +159,9 @@ __global__ __launch_bounds__(kBlock) void copy_kernel(const uint4* __restrict__ 
     }
 }
 
-template <int L, bool INT8>
-hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t s)
-{
-    using Gm = Geo<L>;
-    const int reps_per_block = (sweep_block<L>() / 64) * Gm::RPWV;
-    const int blocks = (a.n_rep + reps_per_block - 1) / reps_per_block;
-    if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((sweep_kernel<L, INT8>), dim3(blocks), dim3(sweep_block<L>()), 0, s, a);
-    return hipGetLastError();
-}
 
 }  // namespace
 
-hipError_t launch_sweep(int L, int layout, const SweepArgs& a, hipStream_t s)
-{
-    const bool i8 = layout == 0;
-    switch (L) {
-    case 16: return i8 ? launch_sweep_t<16, true>(a, s) : launch_sweep_t<16, false>(a, s);
-    case 32: return i8 ? launch_sweep_t<32, true>(a, s) : launch_sweep_t<32, false>(a, s);
-    case 64: return i8 ? launch_sweep_t<64, true>(a, s) : launch_sweep_t<64, false>(a, s);
-    case 128: return i8 ? launch_sweep_t<128, true>(a, s) : launch_sweep_t<128, false>(a, s);
-    case 256: return i8 ? launch_sweep_t<256, true>(a, s) : launch_sweep_t<256, false>(a, s);
-    default: return hipErrorInvalidValue;
-    }
-}
 
 hipError_t launch_stats(const int32_t* E, const int32_t* M, int32_t n, const uint32_t* n_dev, int32_t N,
                         DevStats* st, uint32_t* hist, int32_t nbins, int record, DevMhr mhr, StatsPart* parts,
