@@ -110,6 +110,7 @@ struct pa_run {
     hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;  // sweep timing in pa_anneal (created on first use)
     std::vector<double> m_beta, m_lnZ;
     std::vector<int64_t> m_R;
+    std::vector<double> w;  // host scratch: weights per energy bin
 };
 
 namespace {
@@ -180,6 +181,48 @@ pa_status refresh_stats(pa_run* r, bool record)
 }
 
 host::Hist window(const pa_run* r) { return host::hist_window(r->h_hist.data(), r->h_stats, r->N); }
+
+// Queues the resampling of the current population to beta_next into the
+// other ping-pong buffer: Eq. (Q) with the E_min shift and the tables of Eq.
+// (resampling factors) on the host (from the host copy of the statistics),
+// then copy counts, their prefix sum (the total goes to stats->r_new), parent
+// indices and the replica copy.  The scatter and the copy read the total on
+// the device and are clamped to the capacity, so they can run before the
+// host has checked it; nothing of the current buffer changes.
+pa_status queue_resample(pa_run* r, double beta_next, double* lnQ, int32_t* Emin)
+{
+    const host::Hist h = window(r);
+    const int bmin = h.bmin, nwin = h.bmax - h.bmin + 1;
+    *Emin = h.energy(bmin);
+    uint32_t* tab = (uint32_t*)r->pinned;
+    *lnQ = host::resample_tables(h, r->p.R, r->R_cur, beta_next - r->beta, tab, r->w);
+    HIPCHK(hipMemcpyAsync(r->tbl, tab, (size_t)nwin * 8, hipMemcpyHostToDevice, r->stream));
+    uint32_t k0, k1;
+    key_of(r, &k0, &k1);
+    const int32_t n = (int32_t)r->R_cur;
+    const int32_t nblk = (n + pa::kBlock - 1) / pa::kBlock;
+    const int nxt = r->cur ^ 1;
+    HIPCHK(pa::launch_counts(r->E[r->cur], n, r->N, bmin, nwin, r->tbl, (uint32_t)(r->step + 1), k0, k1, r->counts,
+                             r->bsum, r->stream));
+    HIPCHK(pa::launch_scan_blocks(r->bsum, nblk, r->stats, r->stream));
+    HIPCHK(pa::launch_scatter(r->counts, r->bsum, n, r->lo.capacity, r->parent, r->stream));
+    HIPCHK(pa::launch_copy(r->spin[r->cur], r->E[r->cur], r->M[r->cur], r->parent, &r->stats->r_new,
+                           r->lo.capacity, r->lo.rep_bytes, r->spin[nxt], r->E[nxt], r->M[nxt], r->stream));
+    r->counts_n = n;
+    return PA_OK;
+}
+
+// Makes the resampled population current (after its total has been checked).
+void commit_resample(pa_run* r, double beta_next, double lnQ, int64_t R_new)
+{
+    r->cur ^= 1;
+    r->R_cur = R_new;
+    r->step += 1;
+    r->beta = beta_next;
+    r->lnZ += lnQ;
+    r->lnQ_last = lnQ;
+    r->version += 1;
+}
 
 }  // namespace
 
@@ -299,47 +342,20 @@ pa_status pa_resample(pa_run* r, double beta_next, pa_resample_info* out)
     st = refresh_stats(r, false);
     if (st != PA_OK) return st;
 
-    // Eq. (Q) with the E_min shift, and the tables of Eq. (resampling factors).
-    const host::Hist h = window(r);
-    const int bmin = h.bmin, nwin = h.bmax - h.bmin + 1;
-    const int32_t Emin = h.energy(bmin);
-    uint32_t* tab = (uint32_t*)r->pinned;
-    std::vector<double> w;
-    const double lnQ = host::resample_tables(h, r->p.R, r->R_cur, beta_next - r->beta, tab, w);
-    HIPCHK(hipMemcpyAsync(r->tbl, tab, (size_t)nwin * 8, hipMemcpyHostToDevice, r->stream));
-
-    uint32_t k0, k1;
-    key_of(r, &k0, &k1);
-    const int32_t n = (int32_t)r->R_cur;
-    const int32_t nblk = (n + pa::kBlock - 1) / pa::kBlock;
-    const uint32_t step = (uint32_t)(r->step + 1);
-    HIPCHK(pa::launch_counts(r->E[r->cur], n, r->N, bmin, nwin, r->tbl, step, k0, k1, r->counts, r->bsum,
-                             r->stream));
-    HIPCHK(pa::launch_scan_blocks(r->bsum, nblk, r->stats, r->stream));
+    double lnQ;
+    int32_t Emin;
+    st = queue_resample(r, beta_next, &lnQ, &Emin);
+    if (st != PA_OK) return st;
+    // the host waits only for the total; the copy runs on meanwhile
     uint32_t* rn = (uint32_t*)(r->pinned + r->pinned_bytes - 8);
     HIPCHK(hipMemcpyAsync(rn, &r->stats->r_new, 4, hipMemcpyDeviceToHost, r->stream));
     HIPCHK(hipEventRecord(r->ev_rnew, r->stream));
-    // The parent indices and the copy are queued before the host has seen the
-    // total: they read it on the device, are clamped to the capacity and write
-    // only the other buffer, so a rejected population leaves the run as it was.
-    const int nxt = r->cur ^ 1;
-    HIPCHK(pa::launch_scatter(r->counts, r->bsum, n, r->lo.capacity, r->parent, r->stream));
-    HIPCHK(pa::launch_copy(r->spin[r->cur], r->E[r->cur], r->M[r->cur], r->parent, &r->stats->r_new,
-                           r->lo.capacity, r->lo.rep_bytes, r->spin[nxt], r->E[nxt], r->M[nxt], r->stream));
     HIPCHK(hipEventSynchronize(r->ev_rnew));
     const int64_t R_new = *rn;
-    r->counts_n = n;
     r->stats_version = 0;  // the stats block now holds the resampling total
     if (R_new > r->lo.capacity) return PA_ECAPACITY;
     if (R_new == 0) return PA_EEXTINCT;
-
-    r->cur = nxt;
-    r->R_cur = R_new;
-    r->step += 1;
-    r->beta = beta_next;
-    r->lnZ += lnQ;
-    r->lnQ_last = lnQ;
-    r->version += 1;
+    commit_resample(r, beta_next, lnQ, R_new);
     if (out) {
         out->lnQ = lnQ;
         out->R_new = R_new;
@@ -373,7 +389,6 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
     }
     uint32_t k0, k1;
     key_of(r, &k0, &k1);
-    std::vector<double> w;
     int32_t done = 0;
     while (done < max_steps && r->beta < sc->beta_f) {
         if (r->sweeps + (uint64_t)sc->theta >= ((uint64_t)1 << 31)) return PA_EINVAL;
@@ -386,27 +401,18 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
             bn = (i >= nb) ? sc->beta_f : (double)i * sc->dbeta;
             if (bn > sc->beta_f) bn = sc->beta_f;
             if (bn < r->beta) bn = r->beta;
-        } else if (!host::adapt_beta(h, r->p.R, r->R_cur, r->beta, sc->beta_f, sc->alpha_star, &bn, nullptr, w)) {
+        } else if (!host::adapt_beta(h, r->p.R, r->R_cur, r->beta, sc->beta_f, sc->alpha_star, &bn, nullptr, r->w)) {
             return PA_EINVAL;
         }
-        // Eq. (Q) and the tables of Eq. (resampling factors)
-        const int bmin = h.bmin, nwin = h.bmax - h.bmin + 1;
-        uint32_t* tab = (uint32_t*)r->pinned;
-        const double lnQ = host::resample_tables(h, r->p.R, r->R_cur, bn - r->beta, tab, w);
-        HIPCHK(hipMemcpyAsync(r->tbl, tab, (size_t)nwin * 8, hipMemcpyHostToDevice, r->stream));
-        // The whole step is queued before the host sees the new population
-        // size: resampling into the other buffer, the sweeps and the statistics
-        // there all read it on the device.  A rejected step leaves `cur` as is.
-        const int32_t n = (int32_t)r->R_cur;
-        const int32_t nblk = (n + pa::kBlock - 1) / pa::kBlock;
+        // Resampling into the other buffer, the sweeps and the statistics
+        // there are all queued before the host sees the new population size,
+        // which the kernels read on the device; a refused step leaves `cur`.
+        double lnQ;
+        int32_t Emin;
+        st = queue_resample(r, bn, &lnQ, &Emin);
+        if (st != PA_OK) return st;
         const int nxt = r->cur ^ 1;
         const uint32_t* n_dev = &r->stats->r_new;
-        HIPCHK(pa::launch_counts(r->E[r->cur], n, r->N, bmin, nwin, r->tbl, (uint32_t)(r->step + 1), k0, k1,
-                                 r->counts, r->bsum, r->stream));
-        HIPCHK(pa::launch_scan_blocks(r->bsum, nblk, r->stats, r->stream));
-        HIPCHK(pa::launch_scatter(r->counts, r->bsum, n, r->lo.capacity, r->parent, r->stream));
-        HIPCHK(pa::launch_copy(r->spin[r->cur], r->E[r->cur], r->M[r->cur], r->parent, n_dev, r->lo.capacity,
-                               r->lo.rep_bytes, r->spin[nxt], r->E[nxt], r->M[nxt], r->stream));
         if (sc->theta > 0) {
             pa::SweepArgs a;
             std::memset(&a, 0, sizeof(a));
@@ -434,19 +440,13 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
         DevStats hs;
         std::memcpy(&hs, r->pinned, sizeof(DevStats));
         const int64_t R_new = hs.r_new;
-        r->counts_n = n;
         if (R_new > r->lo.capacity || R_new == 0) {
-            r->stats_version = 0;  // the statistics block holds the rejected population
+            r->stats_version = 0;  // the statistics block holds the refused population
             return R_new == 0 ? PA_EEXTINCT : PA_ECAPACITY;
         }
-        r->cur = nxt;
-        r->R_cur = R_new;
-        r->step += 1;
-        r->beta = bn;
-        r->lnZ += lnQ;
-        r->lnQ_last = lnQ;
+        commit_resample(r, bn, lnQ, R_new);
         r->sweeps += (uint64_t)sc->theta;
-        r->version += 2;
+        r->version += 1;
         r->h_stats = hs;
         std::memcpy(r->h_hist.data(), r->pinned + sizeof(DevStats), (size_t)r->nbins * 4);
         if (hs.emin < -2 * r->N || hs.emax > 2 * r->N || hs.emin > hs.emax) {
