@@ -304,12 +304,16 @@ pa_status pa_batch_download_population(pa_batch* b, int32_t run, int8_t* spins, 
 pa_status pa_batch_set_model(pa_batch* b, const float* params, const float* norm);
 
 /* Training pairs logged by the bisection of adaptive (and learned-fallback)
- * steps of all runs: x[k][8] features, t[k] = ln(beta_{i+1} - beta_i).
- * Copies min(cap, count) pairs; *n receives the count. */
+ * steps of all runs: x[k][8] features, t[k] = ln((beta_{i+1} - beta_i) sigma_E)
+ * with sigma_E the energy spread of the population (ln sigma_E = x[k][1]): the
+ * overlap of Sec. 2.3 is a function of dbeta sigma_E to first order, so the
+ * network learns the remaining dependence and the lattice-size scaling comes
+ * from the feature.  Copies min(cap, count) pairs; *n receives the count. */
 pa_status pa_batch_training_pairs(const pa_batch* b, float* x, float* t, int32_t cap, int32_t* n);
 
 /* Features x[8] of one run's population after its last step, whether they are
- * valid, and the model's proposal (ln step) made from them (test hook). */
+ * valid, and the model's output made from them (test hook): the proposed step
+ * is exp(prop - x[1]). */
 pa_status pa_batch_features(const pa_batch* b, int32_t run, float* x, int32_t* valid, float* prop);
 
 /* Learned mode: proposals made and accepted by the exact overlap test. */

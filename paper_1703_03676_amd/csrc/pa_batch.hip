@@ -586,7 +586,7 @@ struct RunHost {
     FeatDev feat;
     double last_dbeta = 0.0;
     int32_t proposals = 0, accepted = 0;
-    std::vector<float> pair_x, pair_t;  // (features, ln step) from the bisection
+    std::vector<float> pair_x, pair_t;  // (features, ln(step sigma_E)) from the bisection
 };
 
 struct pa_batch {
@@ -776,7 +776,7 @@ void record_measurement(RunHost& h)
 // Learned mode: the proposal beta + exp(prop) is accepted when the exact
 // overlap is within alpha_tol of the target (or it reaches beta_f with enough
 // overlap); otherwise the bisection decides.  Every interior bisection root is
-// logged as a training pair (features, ln step).
+// logged as a training pair (features, ln(step sigma_E)).
 bool choose_beta(RunHost& h, const host::Hist& hw, bool model_set, double* beta_next)
 {
     const pa_schedule& s = h.sched;
@@ -788,7 +788,8 @@ bool choose_beta(RunHost& h, const host::Hist& hw, bool model_set, double* beta_
         return true;
     }
     if (s.mode == PA_STEP_LEARNED && model_set && h.feat.valid) {
-        const double d = std::exp((double)h.feat.prop);
+        // the network predicts ln(dbeta sigma_E); x[1] = ln sigma_E
+        const double d = std::exp((double)h.feat.prop - (double)h.feat.x[1]);
         if (std::isfinite(d) && d > 0.0) {
             const double bp = std::min(h.beta + d, s.beta_f);
             if (bp > h.beta) {
@@ -809,7 +810,7 @@ bool choose_beta(RunHost& h, const host::Hist& hw, bool model_set, double* beta_
     }
     if (*beta_next < s.beta_f && h.feat.valid) {
         h.pair_x.insert(h.pair_x.end(), h.feat.x, h.feat.x + 8);
-        h.pair_t.push_back((float)std::log(*beta_next - h.beta));
+        h.pair_t.push_back((float)(std::log(*beta_next - h.beta) + (double)h.feat.x[1]));
     }
     return true;
 }

@@ -5,7 +5,7 @@
 // thread per parameter sums its per-sample terms in sample order, so a
 // training run is reproducible bit for bit.  SGD with momentum updates the FP32
 // master weights and refreshes the BF16 copy used for inference.  The loss is
-// the mean squared error on the normalised log step.
+// the mean squared error on the normalised target.
 #include <algorithm>
 #include <cmath>
 #include <cstring>

@@ -2,7 +2,8 @@
 // Parameter vector (FP32 master copy, 4801 floats):
 //   W1 [64][8] | b1 [64] | W2 [64][64] | b2 [64] | w3 [64] | b3
 // Normalisation (18 floats, not trained): x_mean[8] | x_std[8] | t_mean | t_std.
-// The network maps normalised features to the normalised log step.
+// The network maps normalised features to its normalised target, the log of
+// the temperature step times the energy spread of the population.
 #pragma once
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
@@ -30,7 +31,7 @@ __device__ __forceinline__ float bf16r(float x) { return __bfloat162float(__floa
 // Forward pass of one sample by the 64 threads t = 0..63 of a block (t is the
 // hidden unit).  x: raw features (normalised here); wb: BF16 parameters;
 // norm: normalisation constants; h: 64 floats of shared scratch.  Returns the
-// de-normalised output (log step) in thread 0.
+// de-normalised output in thread 0.
 __device__ __forceinline__ float forward_bf16(const float* x, const __hip_bfloat16* wb, const float* norm, float* h,
                                               int t)
 {
