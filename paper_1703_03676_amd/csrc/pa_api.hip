@@ -186,10 +186,11 @@ host::Hist window(const pa_run* r) { return host::hist_window(r->h_hist.data(), 
 // other ping-pong buffer: Eq. (Q) with the E_min shift and the tables of Eq.
 // (resampling factors) on the host (from the host copy of the statistics),
 // then copy counts, their prefix sum (the total goes to stats->r_new), parent
-// indices and the replica copy.  The scatter and the copy read the total on
-// the device and are clamped to the capacity, so they can run before the
-// host has checked it; nothing of the current buffer changes.
-pa_status queue_resample(pa_run* r, double beta_next, double* lnQ, int32_t* Emin)
+// indices and (with `copy`) the replica copy.  The scatter and the copy read
+// the total on the device and are clamped to the capacity, so they can run
+// before the host has checked it; nothing of the current buffer changes.
+// Without `copy` the caller's next sweep gathers the parents itself.
+pa_status queue_resample(pa_run* r, double beta_next, bool copy, double* lnQ, int32_t* Emin)
 {
     const host::Hist h = window(r);
     const int bmin = h.bmin, nwin = h.bmax - h.bmin + 1;
@@ -206,8 +207,9 @@ pa_status queue_resample(pa_run* r, double beta_next, double* lnQ, int32_t* Emin
                              r->bsum, r->stream));
     HIPCHK(pa::launch_scan_blocks(r->bsum, nblk, r->stats, r->stream));
     HIPCHK(pa::launch_scatter(r->counts, r->bsum, n, r->lo.capacity, r->parent, r->stream));
-    HIPCHK(pa::launch_copy(r->spin[r->cur], r->E[r->cur], r->M[r->cur], r->parent, &r->stats->r_new,
-                           r->lo.capacity, r->lo.rep_bytes, r->spin[nxt], r->E[nxt], r->M[nxt], r->stream));
+    if (copy)
+        HIPCHK(pa::launch_copy(r->spin[r->cur], r->E[r->cur], r->M[r->cur], r->parent, &r->stats->r_new,
+                               r->lo.capacity, r->lo.rep_bytes, r->spin[nxt], r->E[nxt], r->M[nxt], r->stream));
     r->counts_n = n;
     return PA_OK;
 }
@@ -344,7 +346,7 @@ pa_status pa_resample(pa_run* r, double beta_next, pa_resample_info* out)
 
     double lnQ;
     int32_t Emin;
-    st = queue_resample(r, beta_next, &lnQ, &Emin);
+    st = queue_resample(r, beta_next, true, &lnQ, &Emin);
     if (st != PA_OK) return st;
     // the host waits only for the total; the copy runs on meanwhile
     uint32_t* rn = (uint32_t*)(r->pinned + r->pinned_bytes - 8);
@@ -409,7 +411,9 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
         // which the kernels read on the device; a refused step leaves `cur`.
         double lnQ;
         int32_t Emin;
-        st = queue_resample(r, bn, &lnQ, &Emin);
+        // with sweeps, the sweep kernel loads every child from its parent: the
+        // replica copy and the sweep's load are one pass over the store
+        st = queue_resample(r, bn, sc->theta == 0, &lnQ, &Emin);
         if (st != PA_OK) return st;
         const int nxt = r->cur ^ 1;
         const uint32_t* n_dev = &r->stats->r_new;
@@ -421,6 +425,8 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
             a.M = r->M[nxt];
             a.n_rep = r->lo.capacity;
             a.n_dev = n_dev;
+            a.src = r->spin[r->cur];
+            a.parent = r->parent;
             a.nsweeps = sc->theta;
             a.g0 = (uint32_t)r->sweeps;
             a.key0 = k0;

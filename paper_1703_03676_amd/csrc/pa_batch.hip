@@ -205,7 +205,8 @@ __global__ __launch_bounds__(kBlock) void b_copy(const Item* __restrict__ items,
 {
     const Item it = items[blockIdx.x];
     const StepDev st = steps[it.run];
-    if (!st.active || !st.resample || res[it.run].err) return;
+    // a step with sweeps gathers its parents in b_sweep instead
+    if (!st.active || !st.resample || res[it.run].err || st.nsweeps > 0) return;
     const RunDev& rd = runs[it.run];
     const uint32_t chunks = rd.rep_bytes / 16;
     const size_t total = (size_t)res[it.run].r_new * chunks;
@@ -236,6 +237,11 @@ __global__ __launch_bounds__(512) void b_sweep(const Item* __restrict__ items, c
     const RunDev& rd = runs[it.run];
     SweepArgs a;
     a.n_dev = nullptr;
+    // after a resampling, every child is loaded straight from its parent (the
+    // replica copy and the sweep's load are one pass over the store)
+    const bool gather = st.resample && st.nsweeps > 0;
+    a.src = gather ? rd.spin[st.cur] : nullptr;
+    a.parent = gather ? rd.parent : nullptr;
     a.spin = rd.spin[buf];
     a.E = rd.E[buf];
     a.M = rd.M[buf];

@@ -483,20 +483,38 @@ __device__ __forceinline__ uint32_t init_word(int c, uint32_t v, uint32_t j, con
     return pick(philox10(idx >> 2, 0u, j, kStreamInit, a.key0, a.key1), idx & 3u);
 }
 
-// Load the colour-0 / colour-1 words of word index v of replica j.
+// Bytes of one replica in the spin store.
 template <int L, bool INT8>
-__device__ __forceinline__ void load_word(const SweepArgs& a, uint32_t j, uint32_t v, uint32_t& w0, uint32_t& w1)
+constexpr size_t replica_bytes()
+{
+    return INT8 ? (size_t)Geo<L>::N : Geo<L>::BITS_BYTES;
+}
+
+// The stored replica a sweep starts from for slot j: slot j of the store, or,
+// when the sweep follows a resampling (a.parent set), replica parent[j] of the
+// parent store, so that the copy of the resampling and the load of the sweep
+// are one pass.
+template <int L, bool INT8>
+__device__ __forceinline__ const uint8_t* replica_in(const SweepArgs& a, uint32_t j)
+{
+    if (a.parent) return a.src + (size_t)a.parent[j] * replica_bytes<L, INT8>();
+    return a.spin + (size_t)j * replica_bytes<L, INT8>();
+}
+
+// Load the colour-0 / colour-1 words of word index v of the replica at rep.
+template <int L, bool INT8>
+__device__ __forceinline__ void load_word(const uint8_t* rep, uint32_t v, uint32_t& w0, uint32_t& w1)
 {
     using Gm = Geo<L>;
     if constexpr (INT8) {
-        const uint4* base = reinterpret_cast<const uint4*>(a.spin + (size_t)j * Gm::N);
+        const uint4* base = reinterpret_cast<const uint4*>(rep);
         uint32_t ev, od;
         pack64(base + 4 * v, ev, od);
         const uint32_t em = even_row_mask<L>(v);
         w0 = (ev & em) | (od & ~em);
         w1 = (od & em) | (ev & ~em);
     } else {
-        const uint32_t* base = reinterpret_cast<const uint32_t*>(a.spin + (size_t)j * Gm::BITS_BYTES);
+        const uint32_t* base = reinterpret_cast<const uint32_t*>(rep);
         w0 = base[v];
         w1 = base[Gm::NW + v];
     }
@@ -546,7 +564,7 @@ __device__ __forceinline__ void sweep_regs(const SweepArgs& a, const LaneInfo& l
         s0[0] = init_word<L>(0, v, li.j, a);
         s1[0] = init_word<L>(1, v, li.j, a);
     } else if (li.valid) {
-        load_word<L, INT8>(a, li.j, v, s0[0], s1[0]);
+        load_word<L, INT8>(replica_in<L, INT8>(a, li.j), v, s0[0], s1[0]);
     } else {
         s0[0] = s1[0] = 0u;
     }
@@ -637,6 +655,7 @@ __device__ __forceinline__ void sweep_lds(const SweepArgs& a, uint32_t j, uint32
     const int gl = (int)(threadIdx.x & 63u);
 #pragma unroll
     for (int s = 0; s < Gm::SLOTS; ++s) res[s * 64 + gl] = 0u;
+    const uint8_t* in = a.init ? nullptr : replica_in<L, INT8>(a, j);
 #pragma unroll 1
     for (int k = 0; k < Gm::K; ++k) {
         const uint32_t v = (uint32_t)(gl * Gm::K + k);
@@ -645,7 +664,7 @@ __device__ __forceinline__ void sweep_lds(const SweepArgs& a, uint32_t j, uint32
             w0 = init_word<L>(0, v, j, a);
             w1 = init_word<L>(1, v, j, a);
         } else {
-            load_word<L, INT8>(a, j, v, w0, w1);
+            load_word<L, INT8>(in, v, w0, w1);
         }
         rep.at(0, k, gl) = w0;
         rep.at(1, k, gl) = w1;

@@ -45,6 +45,8 @@ struct SweepArgs {
     uint32_t t4h, t4l;      // threshold T_4
     int32_t init;           // 1: draw the initial state instead of loading spins
     const uint32_t* n_dev;  // if set: the population size is min(*n_dev, n_rep), read on the device
+    const uint8_t* src;     // with parent: replica j starts from replica parent[j] of this store
+    const uint32_t* parent; // (the resampling copy fused into the sweep's load); else NULL
 };
 
 // Kernel launchers; each returns the launch status.
