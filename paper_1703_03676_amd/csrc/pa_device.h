@@ -179,21 +179,25 @@ struct Neighbours {
 //   threshold bit 0: plane bit 1 -> above (reject), plane bit 0 -> still tied
 __device__ __forceinline__ void compare_plane(uint32_t x, uint32_t tb, uint32_t cls1, uint32_t& eq, uint32_t& acc)
 {
+    // Every case writes its results with its own three-input operation, so the
+    // compiler cannot pull a shared AND/OR out of the branches (which costs
+    // extra moves on the merge paths).  Truth tables over (a, b, c) with
+    // a = 0xF0, b = 0xCC, c = 0xAA.
     switch (tb) {
     case 0:
-        eq &= ~x;
+        eq = __builtin_amdgcn_bitop3_b32(eq, x, x, 0x30);  // eq & ~x
         break;
     case 3:
-        acc |= eq & ~x;
-        eq &= x;
+        acc = __builtin_amdgcn_bitop3_b32(acc, eq, x, 0xF4);  // acc | (eq & ~x)
+        eq = __builtin_amdgcn_bitop3_b32(eq, x, x, 0xC0);     // eq & x
         break;
     case 2:  // T_2 bit set, T_4 bit clear
-        acc |= eq & cls1 & ~x;
-        eq &= ~(x ^ cls1);
+        acc |= __builtin_amdgcn_bitop3_b32(eq, cls1, x, 0x40);  // eq & cls1 & ~x
+        eq = __builtin_amdgcn_bitop3_b32(eq, x, cls1, 0x90);    // eq & ~(x ^ cls1)
         break;
     default:  // T_4 bit set, T_2 bit clear
-        acc |= eq & ~cls1 & ~x;
-        eq &= x ^ cls1;
+        acc |= __builtin_amdgcn_bitop3_b32(eq, cls1, x, 0x10);  // eq & ~cls1 & ~x
+        eq = __builtin_amdgcn_bitop3_b32(eq, x, cls1, 0x60);    // eq & (x ^ cls1)
         break;
     }
 }
