@@ -216,13 +216,15 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_
     const uint32_t cls1 = any & ~ge2;  // k = 2
     uint32_t eq = ~ge2;                // sites still tied with their threshold
     uint32_t acc = ge2;
-    if (a.t2h > 0xFFFFu) {             // T_2 = 2^32: always accepted
-        acc |= cls1;
-        eq &= ~cls1;
-    }
-    if (a.t4h > 0xFFFFu) {
-        acc |= ~any;
-        eq &= any;
+    if (__builtin_expect((a.t2h | a.t4h) > 0xFFFFu, 0)) {  // a threshold is 2^32 (beta ~ 0)
+        if (a.t2h > 0xFFFFu) {  // T_2 = 2^32: always accepted
+            acc |= cls1;
+            eq &= ~cls1;
+        }
+        if (a.t4h > 0xFFFFu) {
+            acc |= ~any;
+            eq &= any;
+        }
     }
 #pragma unroll
     for (int kk = 0; kk < 4; ++kk) {
