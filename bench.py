@@ -397,6 +397,9 @@ def main():
     ap.add_argument("--layouts", default="bits,int8")
     ap.add_argument("--no-step-calls", action="store_true",
                     help="skip the comparison runs driven one C-ABI call at a time")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="end with one pa_resample of a fresh L=64, R=20000 population, whose replica copy "
+                         "(known bytes) calibrates the HBM counters of a profiling run")
     ap.add_argument("--workload", default="l64",
                     choices=["l64", "l128_adaptive", "batch64", "l256_learned", "resample_l256"],
                     help="l64 (default) is the headline workload; the others print their own JSON line")
@@ -423,6 +426,12 @@ def main():
     layouts = args.layouts.split(",")
     res = {lay: time_layout(pa, torch, lay, args.steps, args.warmup) for lay in layouts}
     steps_cmp = None if args.no_step_calls else time_step_calls(pa, torch, layouts[0], 2)
+    if args.calibration_copy:
+        cal = pa.Run(L, R, seed=9, layout=layouts[0])
+        cal.observables()
+        cal.resample(DBETA)
+        torch.cuda.synchronize()
+        cal.close()
     head = res[layouts[0]]
     achieved = head["sweep_flips_avg"] * SLOTS_PER_FLIP / (head["sweep_ms_avg"] * 1e-3)
     traffic = measured_traffic()
