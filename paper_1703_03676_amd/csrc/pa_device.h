@@ -45,6 +45,67 @@ __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
     return {c0, c1, c2, c3};
 }
 
+// The same function for counters whose words 1..3 are equal on every lane of
+// the wave (only c0 differs).  In the first three rounds some products and
+// xors then involve wave-uniform values only; written as plain xors with the
+// uniform operands combined first, those parts compile to scalar
+// instructions.  The arithmetic is that of philox10.  (The LDS path gains from
+// it; the register path, with its uniform branch per bit plane, measured
+// slower with it and keeps philox10.)
+__device__ __forceinline__ U4 philox10u(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                        uint32_t k1)
+{
+    uint64_t p0, p1;
+    uint32_t n0, n2;
+    // round 1: c1, c2, c3 uniform
+    p0 = (uint64_t)kM0 * c0;
+    p1 = (uint64_t)kM1 * c2;
+    n0 = ((uint32_t)(p1 >> 32) ^ c1) ^ k0;
+    n2 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += kW0;
+    k1 += kW1;
+    // round 2: c0, c1 uniform
+    p0 = (uint64_t)kM0 * c0;
+    p1 = (uint64_t)kM1 * c2;
+    n0 = (uint32_t)(p1 >> 32) ^ (c1 ^ k0);
+    n2 = c3 ^ ((uint32_t)(p0 >> 32) ^ k1);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += kW0;
+    k1 += kW1;
+    // round 3: c3 uniform
+    p0 = (uint64_t)kM0 * c0;
+    p1 = (uint64_t)kM1 * c2;
+    n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+    n2 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += kW0;
+    k1 += kW1;
+#pragma unroll
+    for (int r = 3; r < 10; ++r) {
+        p0 = (uint64_t)kM0 * c0;
+        p1 = (uint64_t)kM1 * c2;
+        n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += kW0;
+        k1 += kW1;
+    }
+    return {c0, c1, c2, c3};
+}
+
 __device__ __forceinline__ uint32_t pick(const U4& v, uint32_t i)
 {
     return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
@@ -294,8 +355,8 @@ __device__ __forceinline__ uint32_t decide8(uint32_t w, const Nb& n, uint32_t v,
     uint32_t acc = ge2 | all2 | all4;
     tie = 0u;
     if (!__any((u2 | u4) != 0u)) return acc;
-    const U4 P0 = philox10(4u * v, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
-    const U4 P1 = philox10(4u * v + 1u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+    const U4 P0 = philox10u(4u * v, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+    const U4 P1 = philox10u(4u * v + 1u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
     const uint32_t pl[8] = {P0.x, P0.y, P0.z, P0.w, P1.x, P1.y, P1.z, P1.w};
     uint32_t b2 = 0u, b4 = 0u, e2 = ~0u, e4 = ~0u;
 #pragma unroll
@@ -321,14 +382,14 @@ __device__ __forceinline__ bool decide_tail(uint32_t v, uint32_t b, bool k2, uin
     const uint32_t th = k2 ? a.t2h : a.t4h;
 #pragma unroll
     for (int kk = 2; kk < 4; ++kk) {
-        const U4 P = philox10(4u * v + (uint32_t)kk, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+        const U4 P = philox10u(4u * v + (uint32_t)kk, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
         const uint32_t x = (((P.x >> b) & 1u) << 3) | (((P.y >> b) & 1u) << 2) | (((P.z >> b) & 1u) << 1) |
                            ((P.w >> b) & 1u);
         const uint32_t t = (th >> (12 - 4 * kk)) & 15u;
         if (x != t) return x < t;
     }
     const uint32_t q = 32u * v + b;
-    const U4 P = philox10(q >> 3, ctr1, j, kStreamSweepLow, a.key0, a.key1);
+    const U4 P = philox10u(q >> 3, ctr1, j, kStreamSweepLow, a.key0, a.key1);
     const uint32_t word = pick(P, (q >> 1) & 3u);
     const uint32_t lo = (q & 1u) ? (word & 0xFFFFu) : (word >> 16);
     return lo < (k2 ? a.t2l : a.t4l);
