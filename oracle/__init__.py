@@ -70,6 +70,8 @@ def load(path):
         "orc_free": (None, [vp]),
         "orc_init": (None, [vp]),
         "orc_thresholds": (None, [dbl, P(u64), P(u64)]),
+        "orc_hb_thresholds": (None, [dbl, P(u64), P(u64)]),
+        "orc_set_heatbath": (None, [vp, i32]),
         "orc_sweep": (None, [vp, i32]),
         "orc_resample": (i32, [vp, dbl, P(dbl), P(ctypes.c_int32)]),
         "orc_alpha": (dbl, [vp, dbl]),
@@ -115,6 +117,13 @@ def thresholds(beta, lib_=None):
     return t2.value, t4.value
 
 
+def hb_thresholds(beta, lib_=None):
+    """Heat-bath thresholds (U_2, U_4) = ceil(2^32 / (1 + exp(2 beta k))), k = 2, 4."""
+    u2, u4 = ctypes.c_uint64(), ctypes.c_uint64()
+    (lib_ or lib()).orc_hb_thresholds(float(beta), ctypes.byref(u2), ctypes.byref(u4))
+    return u2.value, u4.value
+
+
 def tables(N, R, Rprev, hist, dbeta, lib_=None):
     """Resampling tables (base, thr) and ln Q for an energy histogram."""
     hist = np.ascontiguousarray(hist, dtype=np.int64)
@@ -132,13 +141,15 @@ def default_capacity(R):
 class Run:
     """One PA run held by the oracle."""
 
-    def __init__(self, L, R, seed, run_id=0, capacity=0, lib_=None):
+    def __init__(self, L, R, seed, run_id=0, capacity=0, lib_=None, heatbath=False):
         self.L, self.N, self.R = L, L * L, R
         self.capacity = capacity or default_capacity(R)
         self.lib = lib_ or lib()
+        self.heatbath = bool(heatbath)
         self.h = self.lib.orc_new(L, R, self.capacity, seed, run_id)
         if not self.h:
             raise ValueError("invalid oracle parameters")
+        self.lib.orc_set_heatbath(self.h, 1 if self.heatbath else 0)
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -53,6 +53,13 @@
  *       alpha >= alpha*; the result is the low end.
  *   R9  Multi-histogram reweighting uses every measurement taken (one per call
  *       of orc_measure), including the one at beta_0 = 0.
+ *   R10 Heat-bath update (Sec. 2.1 names it as an alternative to Metropolis and
+ *       gives no details): the site takes spin +1 with probability
+ *       e^{beta h} / (e^{beta h} + e^{-beta h}), so with k = s h it flips with
+ *       probability 1 / (1 + e^{2 beta k}).  It flips iff its 32-bit uniform x
+ *       (the same streams as R3) satisfies x < U_k, with
+ *       U_k = ceil(2^32 / (1 + e^{2 beta k})) for k = 2, 4, U_0 = 2^31 and
+ *       U_{-k} = 2^32 - U_k, so that P(flip | k) + P(flip | -k) = 1 exactly.
  */
 #include <math.h>
 #include <stdint.h>
@@ -128,6 +135,7 @@ typedef struct {
     int counts_n;
     int32_t *slot;      /* optional: random-stream slot of each replica in a sweep
                            (NULL: replica j uses slot j); for sampled checks */
+    int heatbath;       /* 0: Metropolis sweeps (R4); 1: heat-bath sweeps (R10) */
     /* multi-histogram accumulators, one bin per energy level */
     int64_t *H, *SA, *SM2;
     unsigned __int128 *SM4;
@@ -232,6 +240,29 @@ void orc_thresholds(double beta, uint64_t *T2, uint64_t *T4)
     *T4 = (uint64_t)ceil(ldexp(exp(-8.0 * beta), 32));
 }
 
+/* Integer heat-bath thresholds of reading R10 for k = 2, 4:
+ * U_k = ceil(2^32 / (1 + exp(2 beta k))); U_0 = 2^31 and U_{-k} = 2^32 - U_k
+ * follow from them. */
+void orc_hb_thresholds(double beta, uint64_t *U2, uint64_t *U4)
+{
+    *U2 = (uint64_t)ceil(ldexp(1.0 / (1.0 + exp(4.0 * beta)), 32));
+    *U4 = (uint64_t)ceil(ldexp(1.0 / (1.0 + exp(8.0 * beta)), 32));
+}
+
+/* Select the update of orc_sweep: 0 Metropolis (R4), 1 heat-bath (R10). */
+void orc_set_heatbath(orc_run *r, int on) { r->heatbath = on ? 1 : 0; }
+
+/* Heat-bath threshold of a site with k = s h (reading R10). */
+static uint64_t hb_threshold(int k, uint64_t U2, uint64_t U4)
+{
+    const uint64_t two32 = (uint64_t)1 << 32;
+    if (k == 0) return two32 / 2;
+    if (k == 2) return U2;
+    if (k == 4) return U4;
+    if (k == -2) return two32 - U2;
+    return two32 - U4;
+}
+
 /* The sixteen SWEEP-HIGH planes of the 32-site word v (colour c, replica slot
  * j, sweep g): four Philox blocks, outputs in order, plane 0 first. */
 static void sweep_planes(const orc_run *r, uint64_t g, int c, int j, uint32_t v, uint32_t planes[16])
@@ -259,13 +290,15 @@ static uint32_t site_uniform(const orc_run *r, uint64_t g, int c, int j, int q, 
 }
 
 /* Step 3 of the algorithm: theta rounds of checkerboard Metropolis updates at
- * the current beta (Sec. 2.1; checkerboard decomposition of Sec. 3).  Sites of
- * one colour are visited word by word in within-colour index order. */
+ * the current beta (Sec. 2.1; checkerboard decomposition of Sec. 3), or of
+ * heat-bath updates (reading R10) when selected.  Sites of one colour are
+ * visited word by word in within-colour index order. */
 void orc_sweep(orc_run *r, int nsweeps)
 {
     int L = r->L, half = r->N / 2, hw = L / 2;
-    uint64_t T2, T4;
+    uint64_t T2, T4, U2, U4;
     orc_thresholds(r->beta, &T2, &T4);
+    orc_hb_thresholds(r->beta, &U2, &U4);
     for (int t = 0; t < nsweeps; ++t) {
         uint64_t g = r->sweeps;
         for (int c = 0; c < 2; ++c)
@@ -283,7 +316,10 @@ void orc_sweep(orc_run *r, int nsweeps)
                                 s[((y + 1) % L) * L + x] + s[((y + L - 1) % L) * L + x];
                         int k = si * h;
                         int flip;
-                        if (k <= 0) {
+                        if (r->heatbath) {
+                            uint64_t U = hb_threshold(k, U2, U4);
+                            flip = ((uint64_t)site_uniform(r, g, c, slot, q, planes) < U);
+                        } else if (k <= 0) {
                             flip = 1;
                         } else {
                             uint64_t T = (k == 2) ? T2 : T4;

@@ -4,7 +4,7 @@ Each case copies the oracle's C source, plants one plausible mistake (a wrong
 constant, sign, index, operand or comparison), builds it on the CPU and runs a
 fast battery of the same pins the oracle tests use: published Philox vectors,
 the exact Boltzmann distribution and exact free energy at L = 4, closed forms at
-beta = 0, resampling normalisation and order, multi-histogram reweighting and
+beta = 0, the heat-bath flip law per class, resampling normalisation and order, multi-histogram reweighting and
 the adaptive-step postcondition.  The unmodified source must pass the battery
 and every mutant must fail it.
 """
@@ -46,6 +46,12 @@ MUTANTS = {
     "mhr_beta_sign": ("- r->m_beta[i] * E;", "+ r->m_beta[i] * E;"),
     "mhr_moment_index": ("mM2 += p * ((double)r->SM2[b] / h);", "mM2 += p * ((double)r->SA[b] / h);"),
     "bisection_side": ("if (orc_alpha(r, mid) >= alpha_star)", "if (orc_alpha(r, mid) < alpha_star)"),
+    "hb_negative_k": ("if (k == -2) return two32 - U2;", "if (k == -2) return U2;"),
+    "hb_zero_k": ("if (k == 0) return two32 / 2;", "if (k == 0) return two32;"),
+    "hb_exponent_sign": ("1.0 / (1.0 + exp(4.0 * beta))", "1.0 / (1.0 + exp(-4.0 * beta))"),
+    "hb_exponent_scale": ("1.0 / (1.0 + exp(8.0 * beta))", "1.0 / (1.0 + exp(4.0 * beta))"),
+    "hb_direction": ("flip = ((uint64_t)site_uniform(r, g, c, slot, q, planes) < U);",
+                     "flip = ((uint64_t)site_uniform(r, g, c, slot, q, planes) > U);"),
 }
 
 
@@ -95,6 +101,34 @@ def battery(lib, full=False):
             chi2 = ((cnt[keep] - m[keep]) ** 2 / m[keep]).sum()
             dof = keep.sum() - 1
             _check(chi2 < dof + 6 * np.sqrt(2 * dof), "boltzmann_L4", failures)
+
+        # heat-bath: flip frequency of each class k of colour 0 (updated first,
+        # against the initial neighbours) and the Boltzmann distribution at L = 4
+        s0 = inputs.random_spins(1500, 8, 31)
+        r = oracle.Run(8, 1500, seed=17, lib_=lib, heatbath=True)
+        r.set_population(s0, beta=0.3)
+        r.sweep(1)
+        s1, _, _ = r.get_population()
+        h = np.roll(s0, 1, 1) + np.roll(s0, -1, 1) + np.roll(s0, 1, 2) + np.roll(s0, -1, 2)
+        yy, xx = np.mgrid[0:8, 0:8]
+        c0 = ((xx + yy) & 1) == 0
+        k = (s0.astype(int) * h)[:, c0]
+        flipped = (s1 != s0)[:, c0]
+        for kk in (-4, -2, 0, 2, 4):
+            p = 1.0 / (1.0 + np.exp(0.6 * kk))
+            sel = k == kk
+            _check(abs(flipped[sel].mean() - p) < 5 * np.sqrt(p * (1 - p) / sel.sum()), "hb_class_rates", failures)
+        r = oracle.Run(4, 4000, seed=23, lib_=lib, heatbath=True)
+        r.set_population(inputs.random_spins(4000, 4, 8), beta=0.5)
+        r.sweep(40)
+        _, E, _ = r.get_population()
+        ex = exact.brute_observables(4, 0.5)
+        cnt = np.array([(E == e).sum() for e in ex["Ev"]])
+        m = ex["pE"] * cnt.sum()
+        keep = m > 5
+        chi2 = ((cnt[keep] - m[keep]) ** 2 / m[keep]).sum()
+        dof = keep.sum() - 1
+        _check(chi2 < dof + 6 * np.sqrt(2 * dof), "hb_boltzmann_L4", failures)
 
         # resampling: zero step, order, normalisation, lnQ
         s0 = inputs.mixed_spins(200, 6, 3)
