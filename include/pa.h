@@ -57,7 +57,8 @@ typedef enum {
 } pa_layout;
 
 enum {
-    PA_FLAG_MHR = 1     /* accumulate the per-energy histograms used by pa_reweight */
+    PA_FLAG_MHR = 1,     /* accumulate the per-energy histograms used by pa_reweight */
+    PA_FLAG_HEATBATH = 2 /* sweeps use the heat-bath update instead of Metropolis (see pa_sweep) */
 };
 
 typedef struct {
@@ -112,7 +113,12 @@ pa_status pa_init(const pa_params* p, void* d_workspace, size_t bytes, void* hip
  * (Sec. 2.1 step 3; Sec. 3 spin updates).  One sweep updates colour (x+y) even,
  * then odd.  A spin with local field h flips if k = s h <= 0, else with
  * probability exp(-2 beta k), decided against an integer threshold
- * ceil(2^32 exp(-2 beta k)).  Updates E_j and M_j.  Asynchronous.
+ * ceil(2^32 exp(-2 beta k)).  With PA_FLAG_HEATBATH the update is heat-bath
+ * instead (Sec. 2.1 names it as an alternative): the spin flips with
+ * probability 1 / (1 + exp(2 beta k)), i.e. iff its 32-bit uniform is below
+ * U_k = ceil(2^32 / (1 + exp(2 beta k))) for k = 2, 4, U_0 = 2^31,
+ * U_{-k} = 2^32 - U_k.  Both use the same random streams.  Updates E_j and
+ * M_j.  Asynchronous.
  * Errors: PA_EINVAL (nsweeps < 0), PA_ESTATE, PA_EHIP. */
 pa_status pa_sweep(pa_run* r, int32_t nsweeps);
 

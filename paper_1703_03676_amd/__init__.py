@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libpa.so")
 PA_OK, PA_EINVAL, PA_ENOMEM, PA_ECAPACITY, PA_EHIP, PA_ESTATE, PA_EEXTINCT = 0, -1, -2, -3, -4, -5, -6
 PA_SPIN_INT8, PA_SPIN_BITS = 0, 1
 PA_FLAG_MHR = 1
+PA_FLAG_HEATBATH = 2
 LAYOUTS = {"int8": PA_SPIN_INT8, "bits": PA_SPIN_BITS}
 SUPPORTED_L = (16, 32, 64, 128, 256)
 
@@ -170,9 +171,10 @@ def _check(status, handle=None):
     raise PaError(status, msg)
 
 
-def make_params(L, R, seed, run_id=0, capacity=0, layout="bits", mhr=False):
+def make_params(L, R, seed, run_id=0, capacity=0, layout="bits", mhr=False, heatbath=False):
     return Params(L=int(L), R=int(R), capacity=int(capacity), layout=LAYOUTS[layout] if isinstance(layout, str) else int(layout),
-                  seed=int(seed), run_id=int(run_id), flags=PA_FLAG_MHR if mhr else 0)
+                  seed=int(seed), run_id=int(run_id),
+                  flags=(PA_FLAG_MHR if mhr else 0) | (PA_FLAG_HEATBATH if heatbath else 0))
 
 
 def workspace_bytes(params):
@@ -210,11 +212,12 @@ def weighted_average(runs, N):
 class Run:
     """One PA run on the current GPU (C-ABI handle + torch-owned workspace)."""
 
-    def __init__(self, L, R, seed, run_id=0, capacity=0, layout="bits", mhr=False, stream=None, device=None):
+    def __init__(self, L, R, seed, run_id=0, capacity=0, layout="bits", mhr=False, stream=None, device=None,
+                 heatbath=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU available: libpa runs on the GPU only")
-        self.params = make_params(L, R, seed, run_id, capacity, layout, mhr)
+        self.params = make_params(L, R, seed, run_id, capacity, layout, mhr, heatbath)
         nbytes = workspace_bytes(self.params)
         if nbytes == 0:
             raise PaError(PA_EINVAL, "invalid parameters")
@@ -338,7 +341,7 @@ class Batch:
     """Many independent PA runs advanced together (one graph replay per step).
 
     runs: list of dicts with keys L, R, seed and optional run_id, capacity,
-    layout, mhr.  schedules: list of dicts for make_schedule (or one dict for
+    layout, mhr, heatbath.  schedules: list of dicts for make_schedule (or one dict for
     all runs)."""
 
     def __init__(self, runs, schedules, stream=None, device=None):
@@ -350,7 +353,8 @@ class Batch:
             schedules = [schedules] * n
         self.specs = [dict(r) for r in runs]
         self.params = (Params * n)(*[make_params(r["L"], r["R"], r["seed"], r.get("run_id", 0), r.get("capacity", 0),
-                                                 r.get("layout", "bits"), r.get("mhr", False)) for r in runs])
+                                                 r.get("layout", "bits"), r.get("mhr", False),
+                                                 r.get("heatbath", False)) for r in runs])
         self.sched = (Schedule * n)(*[make_schedule(**sc) for sc in schedules])
         nbytes = lib().pa_batch_workspace_bytes(self.params, n)
         if nbytes == 0:

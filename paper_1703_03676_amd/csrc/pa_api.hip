@@ -47,7 +47,7 @@ bool make_layout(const pa_params* p, Layout* lo)
 {
     if (!p || !lattice_supported(p->L) || p->R < 1) return false;
     if (p->layout != PA_SPIN_INT8 && p->layout != PA_SPIN_BITS) return false;
-    if (p->flags & ~(uint32_t)PA_FLAG_MHR) return false;
+    if (p->flags & ~(uint32_t)(PA_FLAG_MHR | PA_FLAG_HEATBATH)) return false;
     const int64_t cap = p->capacity ? p->capacity : default_capacity(p->R);
     if (cap < p->R || cap > (int64_t)1 << 30) return false;
     const int64_t N = (int64_t)p->L * p->L;
@@ -151,9 +151,10 @@ pa_status launch_sweeps(pa_run* r, int32_t nsweeps, bool init)
     a.nsweeps = nsweeps;
     a.g0 = (uint32_t)r->sweeps;
     key_of(r, &a.key0, &a.key1);
-    host::thresholds(r->beta, &a.t2h, &a.t2l, &a.t4h, &a.t4l);
+    const bool hb = (r->p.flags & PA_FLAG_HEATBATH) != 0;
+    host::sweep_thresholds(hb, r->beta, &a.t2h, &a.t2l, &a.t4h, &a.t4l);
     a.init = init ? 1 : 0;
-    HIPCHK(pa::launch_sweep(r->L, r->p.layout, a, r->stream));
+    HIPCHK(pa::launch_sweep(r->L, r->p.layout, hb, a, r->stream));
     return PA_OK;
 }
 
@@ -431,10 +432,11 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
             a.g0 = (uint32_t)r->sweeps;
             a.key0 = k0;
             a.key1 = k1;
-            host::thresholds(bn, &a.t2h, &a.t2l, &a.t4h, &a.t4l);
+            const bool hb = (r->p.flags & PA_FLAG_HEATBATH) != 0;
+            host::sweep_thresholds(hb, bn, &a.t2h, &a.t2l, &a.t4h, &a.t4l);
             const bool timed = sweep_ms && done < cap;
             if (timed) HIPCHK(hipEventRecord(r->ev_t0, r->stream));
-            HIPCHK(pa::launch_sweep(r->L, r->p.layout, a, r->stream));
+            HIPCHK(pa::launch_sweep(r->L, r->p.layout, hb, a, r->stream));
             if (timed) HIPCHK(hipEventRecord(r->ev_t1, r->stream));
         }
         HIPCHK(pa::launch_stats_reset(r->stats, r->hist, r->nbins, r->stream));

@@ -31,6 +31,7 @@
 #include <new>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "pa.h"
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(kBlock) void b_copy(const Item* __restrict__ items,
 }
 
 // Item blk covers waves [blk * wpb, (blk + 1) * wpb) of the run (wpb = blockDim.x / 64).
-template <int L, bool INT8>
+template <int L, bool INT8, bool HB>
 __global__ __launch_bounds__(512) void b_sweep(const Item* __restrict__ items, const RunDev* __restrict__ runs,
                                                const StepDev* __restrict__ steps, const ResultDev* __restrict__ res)
 {
@@ -256,7 +257,7 @@ __global__ __launch_bounds__(512) void b_sweep(const Item* __restrict__ items, c
     a.t4l = st.t4l;
     a.init = st.init;
     const int wpb = (int)(blockDim.x >> 6);
-    sweep_waves<L, INT8>(a, it.blk * wpb, wpb, lds_dyn);
+    sweep_waves<L, INT8, HB>(a, it.blk * wpb, wpb, lds_dyn);
 }
 
 __global__ __launch_bounds__(kBlock) void b_stats_reset(const RunDev* __restrict__ runs,
@@ -390,7 +391,7 @@ bool valid_params(const pa_params& p)
 {
     if (!lattice_supported(p.L) || p.R < 1) return false;
     if (p.layout != PA_SPIN_INT8 && p.layout != PA_SPIN_BITS) return false;
-    if (p.flags & ~(uint32_t)PA_FLAG_MHR) return false;
+    if (p.flags & ~(uint32_t)(PA_FLAG_MHR | PA_FLAG_HEATBATH)) return false;
     const int64_t cap = p.capacity ? p.capacity : default_capacity(p.R);
     return cap >= p.R && cap <= ((int64_t)1 << 30);
 }
@@ -425,9 +426,13 @@ struct BatchLayout {
 };
 
 struct Group {
-    int L, layout, wpb;
+    int L, layout;
+    bool hb;  // heat-bath runs (PA_FLAG_HEATBATH)
+    int wpb;
     size_t item_off, n_items;
 };
+
+bool heatbath(const pa_params& p) { return (p.flags & PA_FLAG_HEATBATH) != 0; }
 
 bool make_batch_layout(const pa_params* runs, int nruns, BatchLayout* bl)
 {
@@ -639,27 +644,38 @@ pa_status fail_hip(pa_batch* b, hipError_t e, const char* what)
         if (e_ != hipSuccess) return fail_hip(b, e_, #expr);  \
     } while (0)
 
-template <int L, bool INT8>
+template <int L, bool INT8, bool HB>
 hipError_t launch_group_t(const Item* items, size_t n, int wpb, const RunDev* rd, const StepDev* st,
                           const ResultDev* rs, hipStream_t s)
 {
     using Gm = pa::dev::Geo<L>;
     const size_t lds = (size_t)Gm::lds_words(wpb) * 4;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL((b_sweep<L, INT8>), dim3((unsigned)n), dim3(64 * wpb), lds, s, items, rd, st, rs);
+    hipLaunchKernelGGL((b_sweep<L, INT8, HB>), dim3((unsigned)n), dim3(64 * wpb), lds, s, items, rd, st, rs);
     return hipGetLastError();
 }
 
-hipError_t launch_group(int L, int layout, const Item* items, size_t n, int wpb, const RunDev* rd, const StepDev* st,
+template <int L>
+hipError_t launch_group_l(bool i8, bool hb, const Item* items, size_t n, int wpb, const RunDev* rd,
+                          const StepDev* st, const ResultDev* rs, hipStream_t s)
+{
+    if (hb)
+        return i8 ? launch_group_t<L, true, true>(items, n, wpb, rd, st, rs, s)
+                  : launch_group_t<L, false, true>(items, n, wpb, rd, st, rs, s);
+    return i8 ? launch_group_t<L, true, false>(items, n, wpb, rd, st, rs, s)
+              : launch_group_t<L, false, false>(items, n, wpb, rd, st, rs, s);
+}
+
+hipError_t launch_group(const Group& g, const Item* items, size_t n, int wpb, const RunDev* rd, const StepDev* st,
                         const ResultDev* rs, hipStream_t s)
 {
-    const bool i8 = layout == PA_SPIN_INT8;
-    switch (L) {
-    case 16: return i8 ? launch_group_t<16, true>(items, n, wpb, rd, st, rs, s) : launch_group_t<16, false>(items, n, wpb, rd, st, rs, s);
-    case 32: return i8 ? launch_group_t<32, true>(items, n, wpb, rd, st, rs, s) : launch_group_t<32, false>(items, n, wpb, rd, st, rs, s);
-    case 64: return i8 ? launch_group_t<64, true>(items, n, wpb, rd, st, rs, s) : launch_group_t<64, false>(items, n, wpb, rd, st, rs, s);
-    case 128: return i8 ? launch_group_t<128, true>(items, n, wpb, rd, st, rs, s) : launch_group_t<128, false>(items, n, wpb, rd, st, rs, s);
-    case 256: return i8 ? launch_group_t<256, true>(items, n, wpb, rd, st, rs, s) : launch_group_t<256, false>(items, n, wpb, rd, st, rs, s);
+    const bool i8 = g.layout == PA_SPIN_INT8;
+    switch (g.L) {
+    case 16: return launch_group_l<16>(i8, g.hb, items, n, wpb, rd, st, rs, s);
+    case 32: return launch_group_l<32>(i8, g.hb, items, n, wpb, rd, st, rs, s);
+    case 64: return launch_group_l<64>(i8, g.hb, items, n, wpb, rd, st, rs, s);
+    case 128: return launch_group_l<128>(i8, g.hb, items, n, wpb, rd, st, rs, s);
+    case 256: return launch_group_l<256>(i8, g.hb, items, n, wpb, rd, st, rs, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -688,13 +704,13 @@ size_t sweep_lds_bytes(int L, int wpb)
 }
 
 // Sweep items of one group for a given number of waves per block.
-std::vector<Item> sweep_items(const pa_batch* b, int L, int layout, int wpb)
+std::vector<Item> sweep_items(const pa_batch* b, const Group& g, int wpb)
 {
     std::vector<Item> it;
-    const int per_block = reps_per_wave(L) * wpb;
+    const int per_block = reps_per_wave(g.L) * wpb;
     for (int r = 0; r < b->nruns; ++r) {
         const pa_params& p = b->runs[(size_t)r].p;
-        if (p.L != L || p.layout != layout) continue;
+        if (p.L != g.L || p.layout != g.layout || heatbath(p) != g.hb) continue;
         const int cap = b->lo.runs[(size_t)r].capacity;
         const int nb = (cap + per_block - 1) / per_block;
         for (int k = 0; k < nb; ++k) it.push_back(Item{r, k});
@@ -723,8 +739,7 @@ pa_status enqueue_step(pa_batch* b)
         BCHK(hipGetLastError());
     }
     for (const Group& g : b->groups)
-        BCHK(launch_group(g.L, g.layout, items + g.item_off, g.n_items, g.wpb, b->d_rundev, b->d_steps,
-                          b->d_results, s));
+        BCHK(launch_group(g, items + g.item_off, g.n_items, g.wpb, b->d_rundev, b->d_steps, b->d_results, s));
     hipLaunchKernelGGL(b_stats_reset, dim3((unsigned)b->nruns), dim3(kBlock), 0, s, b->d_rundev, b->d_steps);
     BCHK(hipGetLastError());
     hipLaunchKernelGGL(b_stats, dim3((unsigned)b->n_parent_items), dim3(kBlock), 0, s, items + b->parent_off,
@@ -958,13 +973,13 @@ static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int
         for (size_t k = 0; k < n; ++k) items.push_back(Item{r, (int32_t)k});
     }
     b->n_copy_items = items.size() - b->copy_off;
-    // sweep groups, one per (L, store)
-    std::map<std::pair<int, int>, int> seen;
+    // sweep groups, one per (L, store, update)
+    std::map<std::tuple<int, int, bool>, int> seen;
     for (int r = 0; r < nruns; ++r) {
-        const auto key = std::make_pair(runs[r].L, runs[r].layout);
+        const auto key = std::make_tuple(runs[r].L, runs[r].layout, heatbath(runs[r]));
         if (!seen.count(key)) {
             seen[key] = (int)b->groups.size();
-            b->groups.push_back(Group{runs[r].L, runs[r].layout, 1, 0, 0});
+            b->groups.push_back(Group{runs[r].L, runs[r].layout, heatbath(runs[r]), 1, 0, 0});
         }
     }
     b->pool = new (std::nothrow) Pool((int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency())));
@@ -973,7 +988,7 @@ static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int
     const size_t fixed_items = items.size();
     for (Group& g : b->groups) {
         g.item_off = items.size();
-        const std::vector<Item> it = sweep_items(b, g.L, g.layout, 1);
+        const std::vector<Item> it = sweep_items(b, g, 1);
         items.insert(items.end(), it.begin(), it.end());
         g.n_items = it.size();
     }
@@ -985,7 +1000,7 @@ static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int
     items.resize(fixed_items);
     for (Group& g : b->groups) {
         g.item_off = items.size();
-        const std::vector<Item> it = sweep_items(b, g.L, g.layout, g.wpb);
+        const std::vector<Item> it = sweep_items(b, g, g.wpb);
         items.insert(items.end(), it.begin(), it.end());
         g.n_items = it.size();
     }
@@ -1009,7 +1024,7 @@ static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int
         d.init = 1;
         d.record = (h.p.flags & PA_FLAG_MHR) ? 1 : 0;
         d.n_parent = h.p.R;
-        host::thresholds(0.0, &d.t2h, &d.t2l, &d.t4h, &d.t4l);
+        host::sweep_thresholds(heatbath(h.p), 0.0, &d.t2h, &d.t2l, &d.t4h, &d.t4l);
         h.R_cur = h.p.R;
         h.lnZ = (double)(h.p.L * h.p.L) * std::log(2.0);
     }
@@ -1080,7 +1095,7 @@ pa_status pa_batch_step(pa_batch* b, int32_t* n_active)
         d.step = (uint32_t)(h.step + 1);
         d.g0 = (uint32_t)h.sweeps;
         d.nsweeps = h.sched.theta;
-        host::thresholds(bn, &d.t2h, &d.t2l, &d.t4h, &d.t4l);
+        host::sweep_thresholds(heatbath(h.p), bn, &d.t2h, &d.t2l, &d.t4h, &d.t4l);
         d.bmin = hw.bmin;
         d.nwin = hw.bmax - hw.bmin + 1;
         d.tbl_off = toff[(size_t)r];
@@ -1276,12 +1291,14 @@ namespace {
 struct TuneKey {
     std::string arch;
     int L, layout;
+    bool hb;
     int64_t reps;
     bool operator<(const TuneKey& o) const
     {
         if (arch != o.arch) return arch < o.arch;
         if (L != o.L) return L < o.L;
         if (layout != o.layout) return layout < o.layout;
+        if (hb != o.hb) return hb < o.hb;
         return reps < o.reps;
     }
 };
@@ -1305,11 +1322,11 @@ pa_status autotune(pa_batch* b)
         int64_t reps = 0;
         for (int r = 0; r < b->nruns; ++r) {
             const RunHost& h = b->runs[(size_t)r];
-            if (h.p.L == g.L && h.p.layout == g.layout) reps += h.p.R;
+            if (h.p.L == g.L && h.p.layout == g.layout && heatbath(h.p) == g.hb) reps += h.p.R;
         }
         int64_t bucket = 1;
         while (bucket < reps) bucket <<= 1;
-        const TuneKey key{arch, g.L, g.layout, bucket};
+        const TuneKey key{arch, g.L, g.layout, g.hb, bucket};
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             const auto f = g_tune_cache.find(key);
@@ -1322,28 +1339,28 @@ pa_status autotune(pa_batch* b)
             StepDev& d = sd[r];
             std::memset(&d, 0, sizeof(d));
             const RunHost& h = b->runs[(size_t)r];
-            if (h.p.L != g.L || h.p.layout != g.layout) continue;
+            if (h.p.L != g.L || h.p.layout != g.layout || heatbath(h.p) != g.hb) continue;
             d.active = 1;
             d.init = 1;
             d.cur = 1;  // spare buffer
             d.n_parent = h.p.R;
             d.nsweeps = 4;
             d.g0 = 0x40000000u;
-            host::thresholds(0.44, &d.t2h, &d.t2l, &d.t4h, &d.t4l);
+            host::sweep_thresholds(g.hb, 0.44, &d.t2h, &d.t2l, &d.t4h, &d.t4l);
         }
         BCHK(hipMemcpyAsync(b->d_steps, b->h_steps, b->lo.steps_bytes, hipMemcpyHostToDevice, b->stream));
         float best = 1e30f;
         int best_w = 1;
         for (int wpb : cands) {
             if (sweep_lds_bytes(g.L, wpb) > 65536) continue;  // at most 64 KB of LDS per block
-            it = sweep_items(b, g.L, g.layout, wpb);
+            it = sweep_items(b, g, wpb);
             const size_t off = g.item_off;  // scratch slot: the group's own item range is large enough
             BCHK(hipMemcpyAsync(b->d_items + off, it.data(), it.size() * sizeof(Item), hipMemcpyHostToDevice,
                                 b->stream));
             float t = 0.0f;
             for (int rep = 0; rep < 3; ++rep) {
                 BCHK(hipEventRecord(e0, b->stream));
-                BCHK(launch_group(g.L, g.layout, b->d_items + off, it.size(), wpb, b->d_rundev, b->d_steps,
+                BCHK(launch_group(g, b->d_items + off, it.size(), wpb, b->d_rundev, b->d_steps,
                                   b->d_results, b->stream));
                 BCHK(hipEventRecord(e1, b->stream));
                 BCHK(hipEventSynchronize(e1));

@@ -315,7 +315,72 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_
     return acc;
 }
 
-template <int L, int C>
+// Neighbour classes of the heat-bath update.  With a the number of
+// anti-aligned neighbours, k = s h = 4 - 2a: neg holds the sites with k < 0
+// (a >= 3), zero those with k = 0 (a = 2) and cls1 those with |k| = 2 (a = 1
+// or 3); the remaining sites have |k| = 4.
+struct HbClass {
+    uint32_t neg, zero, cls1;
+};
+
+__device__ __forceinline__ HbClass hb_classes(uint32_t w, const Nb& n)
+{
+    const uint32_t d1 = w ^ n.up, d2 = w ^ n.dn, d3 = w ^ n.same, d4 = w ^ n.side;
+    const uint32_t o12 = d1 | d2, a12 = d1 & d2, o34 = d3 | d4, a34 = d3 & d4;
+    const uint32_t ge1 = o12 | o34;
+    const uint32_t ge2 = a12 | a34 | (o12 & o34);
+    const uint32_t ge3 = (a12 & o34) | (a34 & o12);
+    const uint32_t all4 = a12 & a34;
+    HbClass c;
+    c.neg = ge3;
+    c.zero = ge2 & ~ge3;
+    c.cls1 = (ge1 & ~ge2) | (ge3 & ~all4);
+    return c;
+}
+
+// Heat-bath flip mask of one 32-site word.  A site flips with probability
+// 1 / (1 + e^{2 beta k}): iff its uniform x is below U_k, where U_2 and U_4 (at
+// most 2^31) arrive in the threshold arguments, U_0 = 2^31 and
+// U_{-k} = 2^32 - U_k.  For k < 0, "x < 2^32 - U_|k|" is "not (~x < U_|k|)",
+// so those sites compare the complement of their uniform with U_|k| (the
+// planes and the low half xored with neg) and take the opposite result.  The
+// k = 0 sites are decided by the top bit of x alone.
+__device__ __forceinline__ uint32_t heatbath_mask(uint32_t w, const Nb& n, uint32_t v, uint32_t ctr1, uint32_t j,
+                                                  const SweepArgs& a)
+{
+    const HbClass c = hb_classes(w, n);
+    uint32_t eq = ~c.zero, acc = 0u;
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        if (kk > 0 && !__any(eq != 0u)) break;
+        const U4 P = philox10(4u * v + (uint32_t)kk, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+        const uint32_t pl[4] = {P.x, P.y, P.z, P.w};
+        if (kk == 0) acc = c.zero & ~pl[0];  // U_0 = 2^31: x < U_0 iff its top bit is 0
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int bit = 15 - (4 * kk + q);
+            const uint32_t tb = (((a.t2h >> bit) & 1u) << 1) | ((a.t4h >> bit) & 1u);
+            compare_plane(pl[q] ^ c.neg, tb, c.cls1, eq, acc);
+        }
+    }
+    if (__any(eq != 0u)) {
+        uint32_t tie = eq;
+        while (tie) {
+            const int b = __builtin_ctz(tie);
+            tie &= tie - 1u;
+            const uint32_t q = 32u * v + (uint32_t)b;
+            const U4 P = philox10(q >> 3, ctr1, j, kStreamSweepLow, a.key0, a.key1);
+            const uint32_t word = pick(P, (q >> 1) & 3u);
+            uint32_t lo = (q & 1u) ? (word & 0xFFFFu) : (word >> 16);
+            if ((c.neg >> b) & 1u) lo ^= 0xFFFFu;
+            const uint32_t tl = ((c.cls1 >> b) & 1u) ? a.t2l : a.t4l;
+            if (lo < tl) acc |= 1u << b;
+        }
+    }
+    return acc ^ c.neg;
+}
+
+template <int L, int C, bool HB>
 __device__ __forceinline__ void half_sweep(uint32_t (&own)[Geo<L>::K], const uint32_t (&oth)[Geo<L>::K], int lane,
                                            int gl, uint32_t g, uint32_t j, const SweepArgs& a)
 {
@@ -325,7 +390,10 @@ __device__ __forceinline__ void half_sweep(uint32_t (&own)[Geo<L>::K], const uin
 #pragma unroll
     for (int k = 0; k < Gm::K; ++k) {
         const uint32_t v = (uint32_t)(gl * Gm::K + k);
-        own[k] ^= accept_mask(own[k], nb.get(oth, k), v, ctr1, j, a);
+        if constexpr (HB)
+            own[k] ^= heatbath_mask(own[k], nb.get(oth, k), v, ctr1, j, a);
+        else
+            own[k] ^= accept_mask(own[k], nb.get(oth, k), v, ctr1, j, a);
     }
 }
 
@@ -373,25 +441,58 @@ __device__ __forceinline__ uint32_t decide8(uint32_t w, const Nb& n, uint32_t v,
     return acc;
 }
 
+// Heat-bath form of decide8 (the update of heatbath_mask): the planes of the
+// k < 0 sites are complemented before the comparison with U_|k|, the k = 0
+// sites are decided by plane 0, and the returned mask is xored with `neg`, so a
+// k < 0 site still tied is provisionally flipped and the tail's result (the
+// comparison of the complemented uniform) xored on top gives its decision.
+__device__ __forceinline__ uint32_t decide8_hb(uint32_t w, const Nb& n, uint32_t v, uint32_t ctr1, uint32_t j,
+                                               const SweepArgs& a, uint32_t& tie, uint32_t& cls1, uint32_t& neg)
+{
+    const HbClass c = hb_classes(w, n);
+    cls1 = c.cls1;
+    neg = c.neg;
+    const uint32_t cls2 = ~(c.zero | c.cls1);  // |k| = 4
+    const U4 P0 = philox10u(4u * v, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+    const U4 P1 = philox10u(4u * v + 1u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+    const uint32_t pl[8] = {P0.x, P0.y, P0.z, P0.w, P1.x, P1.y, P1.z, P1.w};
+    uint32_t b2 = 0u, b4 = 0u, e2 = ~0u, e4 = ~0u;
+#pragma unroll
+    for (int p = 7; p >= 0; --p) {
+        const uint32_t y = pl[p] ^ c.neg;
+        const uint32_t m2 = 0u - ((a.t2h >> (15 - p)) & 1u);
+        const uint32_t m4 = 0u - ((a.t4h >> (15 - p)) & 1u);
+        b2 = __builtin_amdgcn_bitop3_b32(y, b2, m2, 0x8E);  // maj(~y, b, t)
+        b4 = __builtin_amdgcn_bitop3_b32(y, b4, m4, 0x8E);
+        e2 = __builtin_amdgcn_bitop3_b32(e2, y, m2, 0x90);  // e & ~(y ^ t)
+        e4 = __builtin_amdgcn_bitop3_b32(e4, y, m4, 0x90);
+    }
+    const uint32_t acc = (c.zero & ~pl[0]) | (c.cls1 & b2) | (cls2 & b4);
+    tie = (c.cls1 & e2) | (cls2 & e4);
+    return acc ^ c.neg;
+}
+
 // Remaining comparison of site b of word v, tied after 8 planes: planes 8..15
 // (Philox blocks 2 and 3, four planes each, compared as nibbles), then the low
-// 16 bits from the SWEEP-LOW stream.  True if the site flips.
-__device__ __forceinline__ bool decide_tail(uint32_t v, uint32_t b, bool k2, uint32_t ctr1, uint32_t j,
+// 16 bits from the SWEEP-LOW stream.  True if the uniform is below the
+// threshold; with ng (heat-bath, k < 0) the uniform's complement is compared.
+__device__ __forceinline__ bool decide_tail(uint32_t v, uint32_t b, bool k2, bool ng, uint32_t ctr1, uint32_t j,
                                             const SweepArgs& a)
 {
     const uint32_t th = k2 ? a.t2h : a.t4h;
+    const uint32_t flip = ng ? 0xFFFFu : 0u;
 #pragma unroll
     for (int kk = 2; kk < 4; ++kk) {
         const U4 P = philox10u(4u * v + (uint32_t)kk, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
-        const uint32_t x = (((P.x >> b) & 1u) << 3) | (((P.y >> b) & 1u) << 2) | (((P.z >> b) & 1u) << 1) |
-                           ((P.w >> b) & 1u);
+        const uint32_t x = ((((P.x >> b) & 1u) << 3) | (((P.y >> b) & 1u) << 2) | (((P.z >> b) & 1u) << 1) |
+                            ((P.w >> b) & 1u)) ^ (flip & 15u);
         const uint32_t t = (th >> (12 - 4 * kk)) & 15u;
         if (x != t) return x < t;
     }
     const uint32_t q = 32u * v + b;
     const U4 P = philox10u(q >> 3, ctr1, j, kStreamSweepLow, a.key0, a.key1);
     const uint32_t word = pick(P, (q >> 1) & 3u);
-    const uint32_t lo = (q & 1u) ? (word & 0xFFFFu) : (word >> 16);
+    const uint32_t lo = ((q & 1u) ? (word & 0xFFFFu) : (word >> 16)) ^ flip;
     return lo < (k2 ? a.t2l : a.t4l);
 }
 
@@ -421,21 +522,23 @@ __device__ __forceinline__ void wave_lds_sync()
 // each), so instead of evaluating the later Philox blocks for every word, the
 // tied sites of the S words of every lane are queued in LDS and decided one per
 // lane.  An entry is  bits 0-4 site | bit 5 class k = 2 | bits 6-11 lane |
-// bits 12-15 slot  (slot: which of the lane's S words); the decisions are
-// ORed into res[slot * 64 + lane].
-__device__ __forceinline__ uint32_t tie_entry(int s, int lane, uint32_t k2bit, uint32_t b)
+// bits 12-15 slot | bit 16 complemented uniform (heat-bath, k < 0)  (slot: which
+// of the lane's S words); the decisions are ORed into res[slot * 64 + lane].
+__device__ __forceinline__ uint32_t tie_entry(int s, int lane, uint32_t k2bit, uint32_t ngbit, uint32_t b)
 {
-    return ((uint32_t)s << 12) | ((uint32_t)lane << 6) | (k2bit << 5) | b;
+    return (ngbit << 16) | ((uint32_t)s << 12) | ((uint32_t)lane << 6) | (k2bit << 5) | b;
 }
 
 // Tie resolution of the wave: queue[QCAP], res[S * 64] (zero on entry and on
 // return).  vj(lane, slot, &v, &j) gives the word and replica of a lane's
-// slot; extra[s] receives the additional flips of the lane's word s.  If the
-// queue would overflow, every lane decides its own tied sites instead.
+// slot; ng[s] marks the sites that compare the complement of their uniform
+// (heat-bath, k < 0; all zero for Metropolis); extra[s] receives the
+// additional flips of the lane's word s.  If the queue would overflow, every
+// lane decides its own tied sites instead.
 template <int S, int QCAP, class VJ>
-__device__ __forceinline__ void resolve_ties_wave(const uint32_t (&tie)[S], const uint32_t (&cls1)[S], int lane,
-                                                  uint32_t ctr1, const SweepArgs& a, uint32_t* queue, uint32_t* res,
-                                                  uint32_t (&extra)[S], const VJ& vj)
+__device__ __forceinline__ void resolve_ties_wave(const uint32_t (&tie)[S], const uint32_t (&cls1)[S],
+                                                  const uint32_t (&ng)[S], int lane, uint32_t ctr1, const SweepArgs& a,
+                                                  uint32_t* queue, uint32_t* res, uint32_t (&extra)[S], const VJ& vj)
 {
 #pragma unroll
     for (int s = 0; s < S; ++s) extra[s] = 0u;
@@ -454,7 +557,7 @@ __device__ __forceinline__ void resolve_ties_wave(const uint32_t (&tie)[S], cons
             while (t) {
                 const uint32_t b = (uint32_t)__builtin_ctz(t);
                 t &= t - 1u;
-                if (decide_tail(v, b, (cls1[s] >> b) & 1u, ctr1, j, a)) extra[s] |= 1u << b;
+                if (decide_tail(v, b, (cls1[s] >> b) & 1u, (ng[s] >> b) & 1u, ctr1, j, a)) extra[s] |= 1u << b;
             }
         }
         return;
@@ -465,7 +568,7 @@ __device__ __forceinline__ void resolve_ties_wave(const uint32_t (&tie)[S], cons
         while (t) {
             const uint32_t b = (uint32_t)__builtin_ctz(t);
             t &= t - 1u;
-            queue[off++] = tie_entry(s, lane, (cls1[s] >> b) & 1u, b);
+            queue[off++] = tie_entry(s, lane, (cls1[s] >> b) & 1u, (ng[s] >> b) & 1u, b);
         }
     }
     wave_lds_sync();
@@ -475,7 +578,7 @@ __device__ __forceinline__ void resolve_ties_wave(const uint32_t (&tie)[S], cons
         const uint32_t b = e & 31u;
         uint32_t v, j;
         vj(owner, s, &v, &j);
-        if (decide_tail(v, b, (e >> 5) & 1u, ctr1, j, a)) atomicOr(&res[s * 64 + owner], 1u << b);
+        if (decide_tail(v, b, (e >> 5) & 1u, (e >> 16) & 1u, ctr1, j, a)) atomicOr(&res[s * 64 + owner], 1u << b);
     }
     wave_lds_sync();
 #pragma unroll
@@ -620,7 +723,7 @@ __device__ __forceinline__ void write_EM(const SweepArgs& a, const LaneInfo& li,
 }
 
 // Register-resident sweep: each lane owns one word per colour (L <= 64).
-template <int L, bool INT8>
+template <int L, bool INT8, bool HB>
 __device__ __forceinline__ void sweep_regs(const SweepArgs& a, const LaneInfo& li)
 {
     using Gm = Geo<L>;
@@ -637,8 +740,8 @@ __device__ __forceinline__ void sweep_regs(const SweepArgs& a, const LaneInfo& l
     }
     for (int t = 0; t < a.nsweeps; ++t) {
         const uint32_t g = a.g0 + (uint32_t)t;
-        half_sweep<L, 0>(s0, s1, li.lane, li.gl, g, li.j, a);
-        half_sweep<L, 1>(s1, s0, li.lane, li.gl, g, li.j, a);
+        half_sweep<L, 0, HB>(s0, s1, li.lane, li.gl, g, li.j, a);
+        half_sweep<L, 1, HB>(s1, s0, li.lane, li.gl, g, li.j, a);
     }
     const Neighbours<L, 0> nb(s1, li.lane, li.gl);
     const Nb n = nb.get(s1, 0);
@@ -681,7 +784,7 @@ struct LdsRep {
 
 // One colour of a sweep on the LDS path: the lane's K words in chunks of
 // SLOTS, each chunk followed by the wave's tie resolution.
-template <int L, int C>
+template <int L, int C, bool HB>
 __device__ __forceinline__ void half_sweep_lds(const LdsRep<L>& rep, int gl, uint32_t g, uint32_t j,
                                                const SweepArgs& a, uint32_t* queue, uint32_t* res)
 {
@@ -691,19 +794,24 @@ __device__ __forceinline__ void half_sweep_lds(const LdsRep<L>& rep, int gl, uin
     const uint32_t ctr1 = 2u * g + (uint32_t)C;
 #pragma unroll 1
     for (int k0 = 0; k0 < Gm::K; k0 += S) {
-        uint32_t tie[S], k2[S], extra[S];
+        uint32_t tie[S], k2[S], ng[S], extra[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int k = k0 + s;
             const Nb n = rep.template nb<C>(k, gl);
             uint32_t& own = rep.at(C, k, gl);
-            own ^= decide8(own, n, (uint32_t)(gl * Gm::K + k), ctr1, j, a, tie[s], k2[s]);
+            if constexpr (HB) {
+                own ^= decide8_hb(own, n, (uint32_t)(gl * Gm::K + k), ctr1, j, a, tie[s], k2[s], ng[s]);
+            } else {
+                own ^= decide8(own, n, (uint32_t)(gl * Gm::K + k), ctr1, j, a, tie[s], k2[s]);
+                ng[s] = 0u;
+            }
         }
         const auto vj = [&](int owner, int s, uint32_t* vo, uint32_t* jo) {
             *vo = (uint32_t)(owner * Gm::K + k0 + s);
             *jo = j;
         };
-        resolve_ties_wave<S, Gm::QCAP>(tie, k2, gl, ctr1, a, queue, res, extra, vj);
+        resolve_ties_wave<S, Gm::QCAP>(tie, k2, ng, gl, ctr1, a, queue, res, extra, vj);
 #pragma unroll
         for (int s = 0; s < S; ++s) rep.at(C, k0 + s, gl) ^= extra[s];
     }
@@ -711,7 +819,7 @@ __device__ __forceinline__ void half_sweep_lds(const LdsRep<L>& rep, int gl, uin
 }
 
 // The wave's LDS: replica [2][NW], then the tie queue and the slot results.
-template <int L, bool INT8>
+template <int L, bool INT8, bool HB>
 __device__ __forceinline__ void sweep_lds(const SweepArgs& a, uint32_t j, uint32_t* lds)
 {
     using Gm = Geo<L>;
@@ -739,8 +847,8 @@ __device__ __forceinline__ void sweep_lds(const SweepArgs& a, uint32_t j, uint32
     wave_lds_sync();
     for (int t = 0; t < a.nsweeps; ++t) {
         const uint32_t g = a.g0 + (uint32_t)t;
-        half_sweep_lds<L, 0>(rep, gl, g, j, a, queue, res);
-        half_sweep_lds<L, 1>(rep, gl, g, j, a, queue, res);
+        half_sweep_lds<L, 0, HB>(rep, gl, g, j, a, queue, res);
+        half_sweep_lds<L, 1, HB>(rep, gl, g, j, a, queue, res);
     }
     uint32_t anti = 0, downs = 0;
 #pragma unroll 1
@@ -769,8 +877,9 @@ constexpr int sweep_block()
 // Sweep entry shared by the single-run and batched kernels, for the block
 // holding waves [wave0, wave0 + wpb) of a run (wpb = blockDim.x / 64); lds is
 // the block's Geo<L>::lds_words(wpb) words (none on the register path).
-// Waves share no barrier: each returns as soon as it holds no replica.
-template <int L, bool INT8>
+// Waves share no barrier: each returns as soon as it holds no replica.  HB
+// selects the heat-bath update instead of Metropolis.
+template <int L, bool INT8, bool HB>
 __device__ __forceinline__ void sweep_waves(const SweepArgs& a, int wave0, int wpb, uint32_t* lds)
 {
     using Gm = Geo<L>;
@@ -785,9 +894,9 @@ __device__ __forceinline__ void sweep_waves(const SweepArgs& a, int wave0, int w
         if constexpr (Gm::REPW == 1) jj = __builtin_amdgcn_readfirstlane(jj);
         li.j = (uint32_t)jj;
         li.valid = jj < a.n_rep;
-        sweep_regs<L, INT8>(a, li);
+        sweep_regs<L, INT8, HB>(a, li);
     } else {
-        sweep_lds<L, INT8>(a, (uint32_t)__builtin_amdgcn_readfirstlane(wave), lds + wib * Gm::WAVE_LDS_WORDS);
+        sweep_lds<L, INT8, HB>(a, (uint32_t)__builtin_amdgcn_readfirstlane(wave), lds + wib * Gm::WAVE_LDS_WORDS);
     }
 }
 

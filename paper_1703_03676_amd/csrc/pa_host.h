@@ -42,6 +42,29 @@ inline void thresholds(double beta, uint32_t* t2h, uint32_t* t2l, uint32_t* t4h,
     *t4l = (uint32_t)(t4 & 0xFFFFu);
 }
 
+// Heat-bath thresholds U_k = ceil(2^32 / (1 + exp(2 beta k))), k = 2, 4: a site
+// with k = s h flips with probability 1 / (1 + e^{2 beta k}) (heat-bath update,
+// the alternative to Metropolis named in Sec. 2.1); U_0 = 2^31 and
+// U_{-k} = 2^32 - U_k are applied in the kernel.  Same split as thresholds().
+inline void hb_thresholds(double beta, uint32_t* u2h, uint32_t* u2l, uint32_t* u4h, uint32_t* u4l)
+{
+    const uint64_t u2 = (uint64_t)std::ceil(std::ldexp(1.0 / (1.0 + std::exp(4.0 * beta)), 32));
+    const uint64_t u4 = (uint64_t)std::ceil(std::ldexp(1.0 / (1.0 + std::exp(8.0 * beta)), 32));
+    *u2h = (uint32_t)(u2 >> 16);
+    *u2l = (uint32_t)(u2 & 0xFFFFu);
+    *u4h = (uint32_t)(u4 >> 16);
+    *u4l = (uint32_t)(u4 & 0xFFFFu);
+}
+
+// The thresholds of a run's update rule at beta.
+inline void sweep_thresholds(bool heatbath, double beta, uint32_t* t2h, uint32_t* t2l, uint32_t* t4h, uint32_t* t4l)
+{
+    if (heatbath)
+        hb_thresholds(beta, t2h, t2l, t4h, t4l);
+    else
+        thresholds(beta, t2h, t2l, t4h, t4l);
+}
+
 // W = sum over occupied bins (ascending) of n(b) w(b), w(b) = exp(-dbeta (E_b - E_min)):
 // the normalisation of Eq. (Q) shifted by E_min.
 inline double weight_sum(const Hist& h, double dbeta, double* w)

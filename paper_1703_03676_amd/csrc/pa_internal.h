@@ -42,7 +42,7 @@ struct SweepArgs {
     uint32_t g0;            // global sweep number of the first sweep
     uint32_t key0, key1;    // Philox key
     uint32_t t2h, t2l;      // threshold T_2 = t2h * 2^16 + t2l  (t2h <= 65536)
-    uint32_t t4h, t4l;      // threshold T_4
+    uint32_t t4h, t4l;      // threshold T_4  (heat-bath: U_2, U_4, each <= 2^31)
     int32_t init;           // 1: draw the initial state instead of loading spins
     const uint32_t* n_dev;  // if set: the population size is min(*n_dev, n_rep), read on the device
     const uint8_t* src;     // with parent: replica j starts from replica parent[j] of this store
@@ -50,7 +50,9 @@ struct SweepArgs {
 };
 
 // Kernel launchers; each returns the launch status.
-hipError_t launch_sweep(int L, int layout, const SweepArgs& a, hipStream_t s);
+// heatbath selects the heat-bath update (thresholds U_2, U_4 in t2*/t4*)
+// instead of Metropolis (T_2, T_4).
+hipError_t launch_sweep(int L, int layout, bool heatbath, const SweepArgs& a, hipStream_t s);
 // Statistics of a population (after launch_stats_reset): histogram, range,
 // moment sums; parts holds ceil(n / kBlock) partials.  With n_dev the size is
 // min(*n_dev, n), read on the device.

@@ -45,8 +45,12 @@ def test_workspace_bytes_validation():
                 pa.make_params(16, 10, 1, layout=7)):
         assert pa.workspace_bytes(bad) == 0
     bad_flags = pa.make_params(16, 10, 1)
-    bad_flags.flags = 2
+    bad_flags.flags = 4
     assert pa.workspace_bytes(bad_flags) == 0
+    # the heat-bath update needs no extra device memory
+    assert pa.workspace_bytes(pa.make_params(64, 20000, 1, heatbath=True)) == n_bits
+    assert pa.workspace_bytes(pa.make_params(64, 20000, 1, heatbath=True, mhr=True)) == \
+        pa.workspace_bytes(pa.make_params(64, 20000, 1, mhr=True))
     for L in pa.SUPPORTED_L:
         assert pa.workspace_bytes(pa.make_params(L, 3, 1)) > 0
 
