@@ -91,12 +91,12 @@ def one_run(pa, torch, seed, layout, sweep_events=None):
     return flips, last
 
 
-def anneal_run(pa, seed, layout, sweeps=None):
+def anneal_run(pa, seed, layout, sweeps=None, heatbath=False):
     """One full run through pa_anneal (the whole schedule in one call, one
     host round trip per temperature step).  The library times every sweep
     launch with HIP events on the run's stream; (ms, flips) pairs are appended
     to `sweeps`."""
-    run = pa.Run(L, R, seed=seed, layout=layout)
+    run = pa.Run(L, R, seed=seed, layout=layout, heatbath=heatbath)
     run.observables()
     obs, ms = run.anneal(beta_f=1.0, dbeta=DBETA, theta=THETA, mode="fixed", sweep_times=True)
     run.close()
@@ -361,6 +361,32 @@ def workload_l256_learned(pa, torch):
     return out
 
 
+def workload_l64_heatbath(pa, torch):
+    """The headline workload (L=64, R=20000, theta=100, 200 fixed steps of
+    dbeta = 0.005, bit store, through pa_anneal) with heat-bath sweeps, next
+    to the same runs with Metropolis sweeps in the same process: run time,
+    sweep kernel time and the free-energy error at beta = 1 against the exact
+    finite-torus value, over three seeds each."""
+    exact_bf = _exact_betaF(L, 1.0)
+    out = {"workload": "L=64, R=20000, theta=100, beta 0->1 in 200 steps of 0.005, bit store, pa_anneal: "
+                       "heat-bath vs Metropolis sweeps"}
+    for name, hb in (("metropolis", False), ("heatbath", True)):
+        anneal_run(pa, 9, "bits", heatbath=hb)  # warm-up
+        torch.cuda.synchronize()
+        sweeps, errs, flips = [], [], 0
+        t0 = time.perf_counter()
+        for seed in (1, 2, 3):
+            f, last = anneal_run(pa, seed, "bits", sweeps, heatbath=hb)
+            flips += f
+            errs.append(abs(last["betaF_per_N"] - exact_bf))
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[name] = {"ms_per_run": 1e3 * t / 3, "flips_per_ns": flips / (t * 1e9),
+                     "sweep_ms_avg": sum(m for m, _ in sweeps) / len(sweeps),
+                     "betaF_per_N_abs_error": errs}
+    return out
+
+
 def workload_resample_l256(pa, torch):
     """Resampling alone at L=256, R=100000 (both stores): 20 steps of dbeta =
     0.0005 from the initial population, no sweeps.  The replica copy moves
@@ -401,7 +427,7 @@ def main():
                     help="end with one pa_resample of a fresh L=64, R=20000 population, whose replica copy "
                          "(known bytes) calibrates the HBM counters of a profiling run")
     ap.add_argument("--workload", default="l64",
-                    choices=["l64", "l128_adaptive", "batch64", "l256_learned", "resample_l256"],
+                    choices=["l64", "l128_adaptive", "batch64", "l256_learned", "resample_l256", "l64_heatbath"],
                     help="l64 (default) is the headline workload; the others print their own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -418,7 +444,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload != "l64":
         fn = {"l128_adaptive": workload_l128_adaptive, "batch64": workload_batch64,
-              "l256_learned": workload_l256_learned, "resample_l256": workload_resample_l256}[args.workload]
+              "l256_learned": workload_l256_learned, "resample_l256": workload_resample_l256,
+              "l64_heatbath": workload_l64_heatbath}[args.workload]
         res = fn(pa, torch)
         res.pop("_model", None)
         print(json.dumps(res), flush=True)
