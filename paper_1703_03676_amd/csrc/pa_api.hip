@@ -18,6 +18,7 @@
 #include "pa.h"
 #include "pa_host.h"
 #include "pa_internal.h"
+#include "pa_launch.h"
 
 using pa::DevMhr;
 using pa::DevStats;
@@ -106,6 +107,8 @@ struct pa_run {
     std::vector<uint32_t> h_hist;
     uint8_t* pinned;
     size_t pinned_bytes;
+    uint32_t* hstats = nullptr;  // pinned: statistics block + histogram window, written by the statistics kernel
+    void* hstats_dev = nullptr;  // device view of hstats
     hipEvent_t ev_rnew = nullptr;  // marks the resampling total in host memory
     hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;  // sweep timing in pa_anneal (created on first use)
     std::vector<double> m_beta, m_lnZ;
@@ -158,6 +161,22 @@ pa_status launch_sweeps(pa_run* r, int32_t nsweeps, bool init)
     return PA_OK;
 }
 
+// Reads the statistics block and the histogram window that the statistics
+// kernel wrote to pinned host memory (after the stream has been synchronised);
+// bins outside [emin, emax] of h_hist are not used.
+pa_status read_host_stats(pa_run* r, DevStats* out)
+{
+    std::memcpy(out, r->hstats, sizeof(DevStats));
+    if (out->emin < -2 * r->N || out->emax > 2 * r->N || out->emin > out->emax) {
+        r->broken = true;
+        r->last_error = "population energies out of range";
+        return PA_ESTATE;
+    }
+    const int b0 = (out->emin + 2 * r->N) / 4, b1 = (out->emax + 2 * r->N) / 4;
+    std::memcpy(r->h_hist.data() + b0, r->hstats + sizeof(DevStats) / 4 + b0, (size_t)(b1 - b0 + 1) * 4);
+    return PA_OK;
+}
+
 // Brings the histogram and the integer sums of the current population to the
 // host.  With `record` the measurement is also added to the multi-histogram
 // accumulators (only then is a cached result not reused).
@@ -166,17 +185,10 @@ pa_status refresh_stats(pa_run* r, bool record)
     if (!record && r->stats_version == r->version) return PA_OK;
     HIPCHK(pa::launch_stats_reset(r->stats, r->hist, r->nbins, r->stream));
     HIPCHK(pa::launch_stats(r->E[r->cur], r->M[r->cur], (int32_t)r->R_cur, nullptr, r->N, r->stats, r->hist,
-                            r->nbins, record ? 1 : 0, r->mhr, r->parts, r->stream));
-    const size_t bytes = sizeof(DevStats) + (size_t)r->nbins * 4;
-    HIPCHK(hipMemcpyAsync(r->pinned, r->stats, bytes, hipMemcpyDeviceToHost, r->stream));
+                            r->nbins, record ? 1 : 0, r->mhr, r->parts, r->hstats_dev, r->stream));
     HIPCHK(hipStreamSynchronize(r->stream));
-    std::memcpy(&r->h_stats, r->pinned, sizeof(DevStats));
-    std::memcpy(r->h_hist.data(), r->pinned + sizeof(DevStats), (size_t)r->nbins * 4);
-    if (r->h_stats.emin < -2 * r->N || r->h_stats.emax > 2 * r->N || r->h_stats.emin > r->h_stats.emax) {
-        r->broken = true;
-        r->last_error = "population energies out of range";
-        return PA_ESTATE;
-    }
+    const pa_status st = read_host_stats(r, &r->h_stats);
+    if (st != PA_OK) return st;
     r->stats_version = r->version;
     return PA_OK;
 }
@@ -190,7 +202,9 @@ host::Hist window(const pa_run* r) { return host::hist_window(r->h_hist.data(), 
 // indices and (with `copy`) the replica copy.  The scatter and the copy read
 // the total on the device and are clamped to the capacity, so they can run
 // before the host has checked it; nothing of the current buffer changes.
-// Without `copy` the caller's next sweep gathers the parents itself.
+// Without `copy` the caller's next sweep gathers the parents itself.  The
+// scatter also clears the statistics block and the histogram, so the
+// statistics of the resampled population need no separate reset.
 pa_status queue_resample(pa_run* r, double beta_next, bool copy, double* lnQ, int32_t* Emin)
 {
     const host::Hist h = window(r);
@@ -202,12 +216,11 @@ pa_status queue_resample(pa_run* r, double beta_next, bool copy, double* lnQ, in
     uint32_t k0, k1;
     key_of(r, &k0, &k1);
     const int32_t n = (int32_t)r->R_cur;
-    const int32_t nblk = (n + pa::kBlock - 1) / pa::kBlock;
     const int nxt = r->cur ^ 1;
     HIPCHK(pa::launch_counts(r->E[r->cur], n, r->N, bmin, nwin, r->tbl, (uint32_t)(r->step + 1), k0, k1, r->counts,
                              r->bsum, r->stream));
-    HIPCHK(pa::launch_scan_blocks(r->bsum, nblk, r->stats, r->stream));
-    HIPCHK(pa::launch_scatter(r->counts, r->bsum, n, r->lo.capacity, r->parent, r->stream));
+    HIPCHK(pa::launch_scatter(r->counts, r->bsum, n, r->lo.capacity, r->parent, r->stats, r->hist, r->nbins,
+                              r->stream));
     if (copy)
         HIPCHK(pa::launch_copy(r->spin[r->cur], r->E[r->cur], r->M[r->cur], r->parent, &r->stats->r_new,
                                r->lo.capacity, r->lo.rep_bytes, r->spin[nxt], r->E[nxt], r->M[nxt], r->stream));
@@ -299,7 +312,15 @@ pa_status pa_init(const pa_params* p, void* d_workspace, size_t bytes, void* hip
         delete r;
         return PA_ENOMEM;
     }
-    if (hipEventCreateWithFlags(&r->ev_rnew, hipEventDisableTiming) != hipSuccess) {
+    if (hipHostMalloc((void**)&r->hstats, sizeof(DevStats) + (size_t)r->nbins * 4, hipHostMallocMapped) !=
+        hipSuccess) {
+        (void)hipHostFree(r->pinned);
+        delete r;
+        return PA_ENOMEM;
+    }
+    if (hipHostGetDevicePointer(&r->hstats_dev, r->hstats, 0) != hipSuccess ||
+        hipEventCreateWithFlags(&r->ev_rnew, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(r->hstats);
         (void)hipHostFree(r->pinned);
         delete r;
         return PA_EHIP;
@@ -439,15 +460,11 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
             HIPCHK(pa::launch_sweep(r->L, r->p.layout, hb, a, r->stream));
             if (timed) HIPCHK(hipEventRecord(r->ev_t1, r->stream));
         }
-        HIPCHK(pa::launch_stats_reset(r->stats, r->hist, r->nbins, r->stream));
+        // (the scatter of queue_resample has cleared the statistics)
         HIPCHK(pa::launch_stats(r->E[nxt], r->M[nxt], r->lo.capacity, n_dev, r->N, r->stats, r->hist, r->nbins, 0,
-                                r->mhr, r->parts, r->stream));
-        const size_t bytes = sizeof(DevStats) + (size_t)r->nbins * 4;
-        HIPCHK(hipMemcpyAsync(r->pinned, r->stats, bytes, hipMemcpyDeviceToHost, r->stream));
+                                r->mhr, r->parts, r->hstats_dev, r->stream));
         HIPCHK(hipStreamSynchronize(r->stream));
-        DevStats hs;
-        std::memcpy(&hs, r->pinned, sizeof(DevStats));
-        const int64_t R_new = hs.r_new;
+        const int64_t R_new = reinterpret_cast<const DevStats*>(r->hstats)->r_new;
         if (R_new > r->lo.capacity || R_new == 0) {
             r->stats_version = 0;  // the statistics block holds the refused population
             return R_new == 0 ? PA_EEXTINCT : PA_ECAPACITY;
@@ -455,20 +472,15 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
         commit_resample(r, bn, lnQ, R_new);
         r->sweeps += (uint64_t)sc->theta;
         r->version += 1;
-        r->h_stats = hs;
-        std::memcpy(r->h_hist.data(), r->pinned + sizeof(DevStats), (size_t)r->nbins * 4);
-        if (hs.emin < -2 * r->N || hs.emax > 2 * r->N || hs.emin > hs.emax) {
-            r->broken = true;
-            r->last_error = "population energies out of range";
-            return PA_ESTATE;
-        }
+        st = read_host_stats(r, &r->h_stats);
+        if (st != PA_OK) return st;
         r->stats_version = r->version;
         // measurement (Eq. (observables)); the multi-histogram record is queued
         // without a wait, since its statistics equal the ones just read
         if (record) {
             HIPCHK(pa::launch_stats_reset(r->stats, r->hist, r->nbins, r->stream));
             HIPCHK(pa::launch_stats(r->E[r->cur], r->M[r->cur], (int32_t)r->R_cur, nullptr, r->N, r->stats, r->hist,
-                                    r->nbins, 1, r->mhr, r->parts, r->stream));
+                                    r->nbins, 1, r->mhr, r->parts, nullptr, r->stream));
             r->m_beta.push_back(r->beta);
             r->m_lnZ.push_back(r->lnZ);
             r->m_R.push_back(r->R_cur);
@@ -567,6 +579,7 @@ pa_status pa_free(pa_run* r)
     if (r->ev_t0) (void)hipEventDestroy(r->ev_t0);
     if (r->ev_t1) (void)hipEventDestroy(r->ev_t1);
     if (r->pinned) (void)hipHostFree(r->pinned);
+    if (r->hstats) (void)hipHostFree(r->hstats);
     delete r;
     return PA_OK;
 }

@@ -3,11 +3,12 @@
 //
 //   stats_kernel   energy histogram, energy range and exact moment sums
 //                  (inputs of Eq. (Q), Eq. (observables), multi-histogram)
-//   counts_kernel  integer copy counts, Eq. (resampling factors)
-//   scan / scatter prefix sum of the counts -> parent index of every child
+//   counts_kernel  integer copy counts, Eq. (resampling factors), block totals
+//   scatter        prefix sum of the counts -> parent index of every child
 //   copy_kernel    replica copy into the other half of the ping-pong store
 //
 #include "pa_device.h"
+#include "pa_launch.h"
 #include "pa_reduce.h"
 
 namespace pa {
@@ -28,11 +29,25 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(const int32_t* __restrict
     stats_block(E, M, n, N, i0, hist, nbins, record != 0, mhr, &parts[blockIdx.x]);
 }
 
+// Second pass; with `host` (pinned host memory, device view) the block also
+// writes the statistics block and the occupied window [emin, emax] of the
+// histogram there (bin b at byte 64 + 4 b), so the host reads them after the
+// kernel without a separate copy.
 __global__ __launch_bounds__(kBlock) void stats_final_kernel(const StatsPart* __restrict__ parts, int32_t n,
-                                                             const uint32_t* n_dev, DevStats* st)
+                                                             const uint32_t* n_dev, DevStats* st,
+                                                             const uint32_t* __restrict__ hist, int32_t N,
+                                                             uint32_t* __restrict__ host)
 {
     if (n_dev) n = min(n, (int32_t)*n_dev);
     stats_final(parts, (n + kBlock - 1) / kBlock, st);
+    if (!host) return;
+    __syncthreads();  // the block's writes of *st are visible to all its threads
+    const uint32_t* sw = reinterpret_cast<const uint32_t*>(st);
+    if (threadIdx.x < sizeof(DevStats) / 4) host[threadIdx.x] = sw[threadIdx.x];
+    const int32_t emin = st->emin, emax = st->emax;
+    if (emin > emax || emin < -2 * N || emax > 2 * N) return;  // the host rejects such statistics
+    uint32_t* h = host + sizeof(DevStats) / 4;
+    for (int b = (emin + 2 * N) / 4 + (int)threadIdx.x; b <= (emax + 2 * N) / 4; b += kBlock) h[b] = hist[b];
 }
 
 __global__ void stats_reset_kernel(DevStats* st, uint32_t* hist, int32_t nbins)
@@ -77,43 +92,43 @@ __global__ __launch_bounds__(kBlock) void counts_kernel(const int32_t* __restric
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
-// Single block: exclusive scan of the block sums in place; total -> st->r_new.
-__global__ __launch_bounds__(1024) void scan_blocks_kernel(uint32_t* bsum, int32_t nblk, DevStats* st)
-{
-    __shared__ uint32_t part[1024];
-    const int t = (int)threadIdx.x;
-    const int per = (nblk + 1023) / 1024;
-    const int lo = t * per, hi = min(nblk, lo + per);
-    uint32_t s = 0;
-    for (int i = lo; i < hi; ++i) s += bsum[i];
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t y = (t >= off) ? part[t - off] : 0u;
-        __syncthreads();
-        part[t] += y;
-        __syncthreads();
-    }
-    uint32_t run = part[t] - s;  // exclusive prefix of this thread's chunk
-    for (int i = lo; i < hi; ++i) {
-        const uint32_t v = bsum[i];
-        bsum[i] = run;
-        run += v;
-    }
-    if (t == 1023) st->r_new = part[1023];
-}
-
 // Parent index of every child; children beyond `cap` are not written (the
-// caller rejects such a population).
+// caller rejects such a population).  The offset of the block's first child is
+// the sum of the totals of the blocks before it (bsum, from counts_kernel), so
+// no separate scan pass is needed; the last block writes the grand total to
+// st->r_new.  The kernel also clears the rest of the statistics block and the
+// histogram, ready for the statistics of the resampled population (the host
+// has read the previous ones).
 __global__ __launch_bounds__(kBlock) void scatter_kernel(const uint32_t* __restrict__ counts,
                                                          const uint32_t* __restrict__ bsum, int32_t n, uint32_t cap,
-                                                         uint32_t* __restrict__ parent)
+                                                         uint32_t* __restrict__ parent, DevStats* st,
+                                                         uint32_t* __restrict__ hist, int32_t nbins)
 {
+    __shared__ uint32_t wpart[kBlock / 64];
+    const int lane = (int)(threadIdx.x & 63u), wid = (int)(threadIdx.x >> 6);
+    uint32_t before = 0;
+    for (int i = (int)threadIdx.x; i < (int)blockIdx.x; i += kBlock) before += bsum[i];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) before += (uint32_t)__shfl_xor((int)before, off);
+    if (lane == 0) wpart[wid] = before;
+    __syncthreads();
+    uint32_t base = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) base += wpart[w];
     const int j = (int)(blockIdx.x * kBlock + threadIdx.x);
     const uint32_t c = (j < n) ? counts[j] : 0u;
     uint32_t total;
-    const uint32_t off = bsum[blockIdx.x] + block_exclusive_scan(c, &total);
+    const uint32_t off = base + block_exclusive_scan(c, &total);
     for (uint32_t k = 0; k < c && off + k < cap; ++k) parent[off + k] = (uint32_t)j;
+    if (threadIdx.x == 0) {
+        if (blockIdx.x == gridDim.x - 1) st->r_new = base + total;
+        if (blockIdx.x == 0) {
+            st->emin = 0x7FFFFFFF;
+            st->emax = (int32_t)0x80000000;
+            st->sumE = st->sumE2 = st->sumAbsM = st->sumM2 = st->sumM4_lo = st->sumM4_hi = 0;
+        }
+    }
+    for (int b = j; b < nbins; b += (int)(gridDim.x * kBlock)) hist[b] = 0;
 }
 
 // Replica copy child <- parent[child] for child < min(*n_new, cap); the size
@@ -165,15 +180,17 @@ __global__ __launch_bounds__(kBlock) void copy_kernel(const uint4* __restrict__ 
 
 hipError_t launch_stats(const int32_t* E, const int32_t* M, int32_t n, const uint32_t* n_dev, int32_t N,
                         DevStats* st, uint32_t* hist, int32_t nbins, int record, DevMhr mhr, StatsPart* parts,
-                        hipStream_t s)
+                        void* host, hipStream_t s)
 {
     const int blocks = (n + kBlock - 1) / kBlock;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(stats_kernel, dim3(blocks), dim3(kBlock), 0, s, E, M, n, n_dev, N, hist, nbins, record, mhr,
                        parts);
-    hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(kBlock), 0, s, (const StatsPart*)parts, n, n_dev, st);
+    hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(kBlock), 0, s, (const StatsPart*)parts, n, n_dev, st,
+                       (const uint32_t*)hist, N, (uint32_t*)host);
     return hipGetLastError();
 }
+
 hipError_t launch_stats_reset(DevStats* st, uint32_t* hist, int32_t nbins, hipStream_t s)
 {
     const int blocks = std::min((nbins + kBlock - 1) / kBlock, 1024);
@@ -199,18 +216,12 @@ hipError_t launch_counts(const int32_t* E, int32_t n, int32_t N, int32_t bmin, i
     return hipGetLastError();
 }
 
-hipError_t launch_scan_blocks(uint32_t* bsum, int32_t nblk, DevStats* st, hipStream_t s)
-{
-    hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, bsum, nblk, st);
-    return hipGetLastError();
-}
-
 hipError_t launch_scatter(const uint32_t* counts, const uint32_t* bsum, int32_t n, int32_t cap, uint32_t* parent,
-                          hipStream_t s)
+                          DevStats* st, uint32_t* hist, int32_t nbins, hipStream_t s)
 {
-    const int blocks = (n + kBlock - 1) / kBlock;
-    if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(kBlock), 0, s, counts, bsum, n, (uint32_t)cap, parent);
+    const int blocks = std::max((n + kBlock - 1) / kBlock, 1);
+    hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(kBlock), 0, s, counts, bsum, n, (uint32_t)cap, parent, st,
+                       hist, nbins);
     return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@
 // created with PA_FLAG_HEATBATH uses the heat-bath update in the same scheme
 // (its own kernel instantiations).
 #include "pa_device.h"
+#include "pa_launch.h"
 
 namespace pa {
 namespace {
