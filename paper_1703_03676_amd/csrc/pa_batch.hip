@@ -271,7 +271,7 @@ __global__ __launch_bounds__(kBlock) void b_stats_reset(const RunDev* __restrict
         s->emin = 0x7FFFFFFF;
         s->emax = (int32_t)0x80000000;
         s->r_new = 0;
-        s->pad = 0;
+        s->done = 0;
         s->sumE = s->sumE2 = s->sumAbsM = s->sumM2 = s->sumM4_lo = s->sumM4_hi = 0;
     }
     for (int b = (int)threadIdx.x; b < rd.nbins; b += kBlock) rd.hist[b] = 0;

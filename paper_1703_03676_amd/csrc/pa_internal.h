@@ -12,7 +12,7 @@ namespace pa {
 struct DevStats {
     int32_t emin, emax;     // energy range of the population
     uint32_t r_new;         // total of the copy counts (resampling)
-    uint32_t pad;
+    uint32_t done;          // blocks of the statistics pass finished (zero between passes)
     uint64_t sumE, sumE2, sumAbsM, sumM2, sumM4_lo, sumM4_hi;  // two's complement sums
 };
 static_assert(sizeof(DevStats) == 64, "stats block layout");

@@ -17,37 +17,54 @@ namespace {
 using namespace pa::dev;
 
 // ---------------------------------------------------------------------------
-// Population statistics (histogram, energy range, exact moment sums).
+// Population statistics (histogram, energy range, exact moment sums).  Every
+// block adds its replicas to the histogram and writes its partial sums; the
+// block that finishes last (counted in st->done) sums the partials into *st.
+// With `host` (pinned host memory, device view) that block also writes the
+// statistics block and the occupied window [emin, emax] of the histogram there
+// (bin b at byte 64 + 4 b), so the host reads them after the kernel without a
+// separate copy.
 // ---------------------------------------------------------------------------
+// Sums the partials into *st, clears the block counter and, with `host`,
+// publishes the statistics block and the histogram window there.  Called by
+// every thread of the one block that finalises.
+__device__ __forceinline__ void stats_publish(const StatsPart* parts, int nparts, DevStats* st, const uint32_t* hist,
+                                              int32_t N, uint32_t* host)
+{
+    stats_final(parts, nparts, st);
+    __syncthreads();  // *st written by thread 0 is visible to the block
+    if (threadIdx.x == 0) st->done = 0u;
+    if (!host) return;
+    const uint32_t* sw = reinterpret_cast<const uint32_t*>(st);
+    if (threadIdx.x < sizeof(DevStats) / 4) host[threadIdx.x] = (threadIdx.x == 3) ? 0u : sw[threadIdx.x];
+    const int32_t emin = st->emin, emax = st->emax;
+    if (emin > emax || emin < -2 * N || emax > 2 * N) return;  // empty or invalid: the host uses no bins
+    uint32_t* h = host + sizeof(DevStats) / 4;
+    for (int b = (emin + 2 * N) / 4 + (int)threadIdx.x; b <= (emax + 2 * N) / 4; b += kBlock) h[b] = hist[b];
+}
+
 __global__ __launch_bounds__(kBlock) void stats_kernel(const int32_t* __restrict__ E, const int32_t* __restrict__ M,
                                                        int32_t n, const uint32_t* n_dev, int32_t N, uint32_t* hist,
-                                                       int32_t nbins, int record, DevMhr mhr, StatsPart* parts)
+                                                       int32_t nbins, int record, DevMhr mhr, StatsPart* parts,
+                                                       DevStats* st, uint32_t* __restrict__ host)
 {
+    __shared__ uint32_t last;
     if (n_dev) n = min(n, (int32_t)*n_dev);
+    const int nparts = (n + kBlock - 1) / kBlock;
+    if (nparts == 0) {  // empty population (a refused step): block 0 publishes the empty statistics
+        if (blockIdx.x == 0) stats_publish(parts, 0, st, hist, N, host);
+        return;
+    }
     const int32_t i0 = (int32_t)(blockIdx.x * kBlock);
     if (i0 >= n) return;  // uniform per block
     stats_block(E, M, n, N, i0, hist, nbins, record != 0, mhr, &parts[blockIdx.x]);
-}
-
-// Second pass; with `host` (pinned host memory, device view) the block also
-// writes the statistics block and the occupied window [emin, emax] of the
-// histogram there (bin b at byte 64 + 4 b), so the host reads them after the
-// kernel without a separate copy.
-__global__ __launch_bounds__(kBlock) void stats_final_kernel(const StatsPart* __restrict__ parts, int32_t n,
-                                                             const uint32_t* n_dev, DevStats* st,
-                                                             const uint32_t* __restrict__ hist, int32_t N,
-                                                             uint32_t* __restrict__ host)
-{
-    if (n_dev) n = min(n, (int32_t)*n_dev);
-    stats_final(parts, (n + kBlock - 1) / kBlock, st);
-    if (!host) return;
-    __syncthreads();  // the block's writes of *st are visible to all its threads
-    const uint32_t* sw = reinterpret_cast<const uint32_t*>(st);
-    if (threadIdx.x < sizeof(DevStats) / 4) host[threadIdx.x] = sw[threadIdx.x];
-    const int32_t emin = st->emin, emax = st->emax;
-    if (emin > emax || emin < -2 * N || emax > 2 * N) return;  // the host rejects such statistics
-    uint32_t* h = host + sizeof(DevStats) / 4;
-    for (int b = (emin + 2 * N) / 4 + (int)threadIdx.x; b <= (emax + 2 * N) / 4; b += kBlock) h[b] = hist[b];
+    __threadfence();  // this block's partial and histogram updates, device-wide
+    __syncthreads();
+    if (threadIdx.x == 0) last = (atomicAdd(&st->done, 1u) == (uint32_t)(nparts - 1)) ? 1u : 0u;
+    __syncthreads();
+    if (!last) return;  // uniform per block
+    __threadfence();    // every other block's updates are visible to this one
+    stats_publish(parts, nparts, st, hist, N, host);
 }
 
 __global__ void stats_reset_kernel(DevStats* st, uint32_t* hist, int32_t nbins)
@@ -56,6 +73,7 @@ __global__ void stats_reset_kernel(DevStats* st, uint32_t* hist, int32_t nbins)
     if (i == 0) {
         st->emin = 0x7FFFFFFF;
         st->emax = (int32_t)0x80000000;
+        st->done = 0u;
         st->sumE = st->sumE2 = st->sumAbsM = st->sumM2 = st->sumM4_lo = st->sumM4_hi = 0;
     }
     for (int b = i; b < nbins; b += (int)(gridDim.x * blockDim.x)) hist[b] = 0;
@@ -125,6 +143,7 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(const uint32_t* __restr
         if (blockIdx.x == 0) {
             st->emin = 0x7FFFFFFF;
             st->emax = (int32_t)0x80000000;
+            st->done = 0u;
             st->sumE = st->sumE2 = st->sumAbsM = st->sumM2 = st->sumM4_lo = st->sumM4_hi = 0;
         }
     }
@@ -185,9 +204,7 @@ hipError_t launch_stats(const int32_t* E, const int32_t* M, int32_t n, const uin
     const int blocks = (n + kBlock - 1) / kBlock;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(stats_kernel, dim3(blocks), dim3(kBlock), 0, s, E, M, n, n_dev, N, hist, nbins, record, mhr,
-                       parts);
-    hipLaunchKernelGGL(stats_final_kernel, dim3(1), dim3(kBlock), 0, s, (const StatsPart*)parts, n, n_dev, st,
-                       (const uint32_t*)hist, N, (uint32_t*)host);
+                       parts, st, (uint32_t*)host);
     return hipGetLastError();
 }
 
