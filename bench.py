@@ -387,6 +387,46 @@ def workload_l64_heatbath(pa, torch):
     return out
 
 
+def _paper_run(pa, torch, L_, R_, theta, layout):
+    """One full run beta 0 -> 1 in 200 fixed steps of 0.005 through pa_anneal;
+    returns (t_SF in ns, share of the run spent in sweep launches)."""
+    run = pa.Run(L_, R_, seed=1, layout=layout)
+    run.observables()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    obs, ms = run.anneal(beta_f=1.0, dbeta=0.005, theta=theta, mode="fixed", cap=256, sweep_times=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    run.close()
+    flips = sum(L_ * L_ * theta * o["R"] for o in obs)
+    return 1e9 * t / flips, 1e-3 * sum(ms) / t
+
+
+def workload_paper_tables(pa, torch):
+    """The paper's own timing tables re-run on one MI355X: t_SF = run time /
+    attempted flips for full runs beta 0 -> 1 (200 steps of dbeta = 0.005; the
+    paper does not state its dbeta), Table 2 (theta = 500, R = 50000,
+    L = 16 ... 256, both stores) and Table 3 (L = 128, R in {2k, 10k, 50k,
+    100k}, theta in {1, 5, 10, 50, 100, 200, 500}, bit store), with the share
+    of each run spent in sweep launches (the quantity of Table 4)."""
+    out = {"workload": "paper Tables 2-4 shapes: full runs beta 0->1, 200 steps of dbeta=0.005, pa_anneal",
+           "table2": {}, "table3": {}}
+    _paper_run(pa, torch, 64, 2000, 10, "bits")  # warm-up
+    for L_ in (16, 32, 64, 128, 256):
+        for layout in ("int8", "bits"):
+            tsf, share = _paper_run(pa, torch, L_, 50000, 500, layout)
+            out["table2"]["L=%d %s" % (L_, layout)] = {"t_SF_ns": tsf, "flips_per_ns": 1.0 / tsf,
+                                                       "sweep_share": share}
+            print("table2 L=%d %s t_SF %.5f ns" % (L_, layout, tsf), file=sys.stderr, flush=True)
+    for R_ in (2000, 10000, 50000, 100000):
+        for theta in (1, 5, 10, 50, 100, 200, 500):
+            tsf, share = _paper_run(pa, torch, 128, R_, theta, "bits")
+            out["table3"]["R=%d theta=%d" % (R_, theta)] = {"t_SF_ns": tsf, "flips_per_ns": 1.0 / tsf,
+                                                           "sweep_share": share}
+            print("table3 R=%d theta=%d t_SF %.5f ns" % (R_, theta, tsf), file=sys.stderr, flush=True)
+    return out
+
+
 def workload_resample_l256(pa, torch):
     """Resampling alone at L=256, R=100000 (both stores): 20 steps of dbeta =
     0.0005 from the initial population, no sweeps.  The replica copy moves
@@ -427,7 +467,8 @@ def main():
                     help="end with one pa_resample of a fresh L=64, R=20000 population, whose replica copy "
                          "(known bytes) calibrates the HBM counters of a profiling run")
     ap.add_argument("--workload", default="l64",
-                    choices=["l64", "l128_adaptive", "batch64", "l256_learned", "resample_l256", "l64_heatbath"],
+                    choices=["l64", "l128_adaptive", "batch64", "l256_learned", "resample_l256", "l64_heatbath",
+                             "paper_tables"],
                     help="l64 (default) is the headline workload; the others print their own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -445,7 +486,7 @@ def main():
     if args.workload != "l64":
         fn = {"l128_adaptive": workload_l128_adaptive, "batch64": workload_batch64,
               "l256_learned": workload_l256_learned, "resample_l256": workload_resample_l256,
-              "l64_heatbath": workload_l64_heatbath}[args.workload]
+              "l64_heatbath": workload_l64_heatbath, "paper_tables": workload_paper_tables}[args.workload]
         res = fn(pa, torch)
         res.pop("_model", None)
         print(json.dumps(res), flush=True)
