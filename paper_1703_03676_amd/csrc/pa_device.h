@@ -287,16 +287,29 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_
             eq &= any;
         }
     }
+    if (__any(eq != 0u)) {
+        // blocks 0 and 1 are computed together (two independent chains), since
+        // the first four planes leave some site of the wave tied almost surely
+        const U4 P0 = philox10(4u * v, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+        const U4 P1 = philox10(4u * v + 1u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+        const uint32_t pl[8] = {P0.x, P0.y, P0.z, P0.w, P1.x, P1.y, P1.z, P1.w};
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) {
-        if (!__any(eq != 0u)) break;
-        const U4 P = philox10(4u * v + (uint32_t)kk, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
-        const uint32_t pl[4] = {P.x, P.y, P.z, P.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int bit = 15 - (4 * kk + q);
+        for (int q = 0; q < 8; ++q) {
+            const int bit = 15 - q;
             const uint32_t tb = (((a.t2h >> bit) & 1u) << 1) | ((a.t4h >> bit) & 1u);
             compare_plane(pl[q], tb, cls1, eq, acc);
+        }
+#pragma unroll
+        for (int kk = 2; kk < 4; ++kk) {
+            if (!__any(eq != 0u)) break;
+            const U4 P = philox10(4u * v + (uint32_t)kk, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+            const uint32_t pq[4] = {P.x, P.y, P.z, P.w};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int bit = 15 - (4 * kk + q);
+                const uint32_t tb = (((a.t2h >> bit) & 1u) << 1) | ((a.t4h >> bit) & 1u);
+                compare_plane(pq[q], tb, cls1, eq, acc);
+            }
         }
     }
     if (__any(eq != 0u)) {
