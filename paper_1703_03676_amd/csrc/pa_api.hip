@@ -114,6 +114,7 @@ struct pa_run {
     std::vector<double> m_beta, m_lnZ;
     std::vector<int64_t> m_R;
     std::vector<double> w;  // host scratch: weights per energy bin
+    host::WeightTable wpre; // weights of the next fixed step, filled while the GPU sweeps
 };
 
 namespace {
@@ -211,7 +212,7 @@ pa_status queue_resample(pa_run* r, double beta_next, bool copy, double* lnQ, in
     const int bmin = h.bmin, nwin = h.bmax - h.bmin + 1;
     *Emin = h.energy(bmin);
     uint32_t* tab = (uint32_t*)r->pinned;
-    *lnQ = host::resample_tables(h, r->p.R, r->R_cur, beta_next - r->beta, tab, r->w);
+    *lnQ = host::resample_tables(h, r->p.R, r->R_cur, beta_next - r->beta, tab, r->w, &r->wpre);
     HIPCHK(hipMemcpyAsync(r->tbl, tab, (size_t)nwin * 8, hipMemcpyHostToDevice, r->stream));
     uint32_t k0, k1;
     key_of(r, &k0, &k1);
@@ -414,17 +415,20 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
     uint32_t k0, k1;
     key_of(r, &k0, &k1);
     int32_t done = 0;
+    // fixed schedule: inverse temperature of step i, not below the one before
+    auto fixed_beta = [&](int64_t i, double prev) {
+        const int64_t nb = std::max<int64_t>(1, std::llround(sc->beta_f / sc->dbeta));
+        double b = (i >= nb) ? sc->beta_f : (double)i * sc->dbeta;
+        if (b > sc->beta_f) b = sc->beta_f;
+        return b < prev ? prev : b;
+    };
     while (done < max_steps && r->beta < sc->beta_f) {
         if (r->sweeps + (uint64_t)sc->theta >= ((uint64_t)1 << 31)) return PA_EINVAL;
         // next inverse temperature from the host copy of the current statistics
         const host::Hist h = window(r);
         double bn;
         if (sc->mode == PA_STEP_FIXED) {
-            const int64_t nb = std::max<int64_t>(1, std::llround(sc->beta_f / sc->dbeta));
-            const int64_t i = (int64_t)r->step + 1;
-            bn = (i >= nb) ? sc->beta_f : (double)i * sc->dbeta;
-            if (bn > sc->beta_f) bn = sc->beta_f;
-            if (bn < r->beta) bn = r->beta;
+            bn = fixed_beta((int64_t)r->step + 1, r->beta);
         } else if (!host::adapt_beta(h, r->p.R, r->R_cur, r->beta, sc->beta_f, sc->alpha_star, &bn, nullptr, r->w)) {
             return PA_EINVAL;
         }
@@ -463,6 +467,13 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
         // (the scatter of queue_resample has cleared the statistics)
         HIPCHK(pa::launch_stats(r->E[nxt], r->M[nxt], r->lo.capacity, n_dev, r->N, r->stats, r->hist, r->nbins, 0,
                                 r->mhr, r->parts, r->hstats_dev, r->stream));
+        if (sc->mode == PA_STEP_FIXED && bn < sc->beta_f) {
+            // while the GPU sweeps: the weights of the next step (its dbeta is
+            // known in advance), over the current window plus a margin
+            const double db = fixed_beta((int64_t)r->step + 2, bn) - bn;
+            const size_t want = (size_t)(h.bmax - h.bmin + 1) * 5 / 4 + 16;
+            if (!r->wpre.covers(db, (int)want)) r->wpre.fill(db, want);
+        }
         HIPCHK(hipStreamSynchronize(r->stream));
         const int64_t R_new = reinterpret_cast<const DevStats*>(r->hstats)->r_new;
         if (R_new > r->lo.capacity || R_new == 0) {

@@ -65,17 +65,35 @@ inline void sweep_thresholds(bool heatbath, double beta, uint32_t* t2h, uint32_t
         thresholds(beta, t2h, t2l, t4h, t4l);
 }
 
+// Weights exp(-dbeta d) for d = 4 k, k = 0, 1, ...: exactly the expression
+// weight_sum evaluates for a bin 4 k above E_min (energies are multiples of 4),
+// so a table filled ahead of time, while the GPU sweeps, gives identical
+// values.
+struct WeightTable {
+    double dbeta = -1.0;
+    std::vector<double> w;
+    void fill(double db, size_t n)
+    {
+        dbeta = db;
+        w.resize(n);
+        for (size_t k = 0; k < n; ++k) w[k] = std::exp(-(db * (double)(int32_t)(4 * k)));
+    }
+    bool covers(double db, int nwin) const { return db == dbeta && (size_t)nwin <= w.size(); }
+};
+
 // W = sum over occupied bins (ascending) of n(b) w(b), w(b) = exp(-dbeta (E_b - E_min)):
-// the normalisation of Eq. (Q) shifted by E_min.
-inline double weight_sum(const Hist& h, double dbeta, double* w)
+// the normalisation of Eq. (Q) shifted by E_min.  With a table that covers the
+// window (same dbeta), its values are used instead of evaluating exp again.
+inline double weight_sum(const Hist& h, double dbeta, double* w, const WeightTable* pre = nullptr)
 {
     const int32_t Emin = h.energy(h.bmin);
+    const double* tw = (pre && pre->covers(dbeta, h.bmax - h.bmin + 1)) ? pre->w.data() : nullptr;
     double W = 0.0;
     for (int b = h.bmin; b <= h.bmax; ++b) {
         const uint32_t n = h.n[b];
         if (n == 0) continue;
         const double d = (double)(h.energy(b) - Emin);
-        const double wb = std::exp(-(dbeta * d));
+        const double wb = tw ? tw[b - h.bmin] : std::exp(-(dbeta * d));
         if (w) w[b - h.bmin] = wb;
         W += (double)n * wb;
     }
@@ -86,10 +104,10 @@ inline double weight_sum(const Hist& h, double dbeta, double* w)
 // floor(tau_hat) and thr = floor(2^32 frac(tau_hat)), tau_hat = R w / W.
 // tab holds 2 entries per bin of the window; returns ln Q of Eq. (Q).
 inline double resample_tables(const Hist& h, int64_t R, int64_t Rprev, double dbeta, uint32_t* tab,
-                              std::vector<double>& w)
+                              std::vector<double>& w, const WeightTable* pre = nullptr)
 {
     w.assign((size_t)(h.bmax - h.bmin + 1), 0.0);
-    const double W = weight_sum(h, dbeta, w.data());
+    const double W = weight_sum(h, dbeta, w.data(), pre);
     for (int b = h.bmin; b <= h.bmax; ++b) {
         uint32_t base = 0, thr = 0;
         if (h.n[b] != 0) {
