@@ -464,6 +464,80 @@ __device__ __forceinline__ uint32_t decide8(uint32_t w, const Nb& n, uint32_t v,
     return acc;
 }
 
+// decide8 for NG words of one lane together: the 8 planes are compared high
+// bit first with one uniform branch per plane over the two threshold bits,
+// shared by the NG words (2-3 operations per word and plane, instead of the 4
+// of the two branch-free chains).  Same acceptances and ties as decide8.
+template <int NG>
+__device__ __forceinline__ void decide8_group(uint32_t (&w)[NG], const Nb (&n)[NG], const uint32_t (&v)[NG],
+                                              uint32_t ctr1, uint32_t j, const SweepArgs& a, uint32_t (&tie)[NG],
+                                              uint32_t (&cls1)[NG])
+{
+    uint32_t eq[NG], acc[NG];
+    uint32_t need = 0u;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        const uint32_t d1 = w[g] ^ n[g].up, d2 = w[g] ^ n[g].dn, d3 = w[g] ^ n[g].same, d4 = w[g] ^ n[g].side;
+        const uint32_t o12 = d1 | d2, a12 = d1 & d2, o34 = d3 | d4, a34 = d3 & d4;
+        const uint32_t ge2 = a12 | a34 | (o12 & o34);
+        const uint32_t any = o12 | o34;
+        cls1[g] = any & ~ge2;
+        const uint32_t cls2 = ~any;
+        const uint32_t all2 = (a.t2h > 0xFFFFu) ? cls1[g] : 0u;
+        const uint32_t all4 = (a.t4h > 0xFFFFu) ? cls2 : 0u;
+        eq[g] = (cls1[g] & ~all2) | (cls2 & ~all4);
+        acc[g] = ge2 | all2 | all4;
+        need |= eq[g];
+    }
+    if (__any(need != 0u)) {
+        uint32_t pl[NG][8];
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            const U4 P0 = philox10u(4u * v[g], ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+            const U4 P1 = philox10u(4u * v[g] + 1u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+            pl[g][0] = P0.x, pl[g][1] = P0.y, pl[g][2] = P0.z, pl[g][3] = P0.w;
+            pl[g][4] = P1.x, pl[g][5] = P1.y, pl[g][6] = P1.z, pl[g][7] = P1.w;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int bit = 15 - q;
+            const uint32_t tb = (((a.t2h >> bit) & 1u) << 1) | ((a.t4h >> bit) & 1u);
+            switch (tb) {
+            case 0:
+#pragma unroll
+                for (int g = 0; g < NG; ++g) eq[g] = __builtin_amdgcn_bitop3_b32(eq[g], pl[g][q], pl[g][q], 0x30);
+                break;
+            case 3:
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    acc[g] = __builtin_amdgcn_bitop3_b32(acc[g], eq[g], pl[g][q], 0xF4);
+                    eq[g] = __builtin_amdgcn_bitop3_b32(eq[g], pl[g][q], pl[g][q], 0xC0);
+                }
+                break;
+            case 2:
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    acc[g] |= __builtin_amdgcn_bitop3_b32(eq[g], cls1[g], pl[g][q], 0x40);
+                    eq[g] = __builtin_amdgcn_bitop3_b32(eq[g], pl[g][q], cls1[g], 0x90);
+                }
+                break;
+            default:
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    acc[g] |= __builtin_amdgcn_bitop3_b32(eq[g], cls1[g], pl[g][q], 0x10);
+                    eq[g] = __builtin_amdgcn_bitop3_b32(eq[g], pl[g][q], cls1[g], 0x60);
+                }
+                break;
+            }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        w[g] ^= acc[g];
+        tie[g] = eq[g];
+    }
+}
+
 // Heat-bath form of decide8 (the update of heatbath_mask): the planes of the
 // k < 0 sites are complemented before the comparison with U_|k|, the k = 0
 // sites are decided by plane 0, and the returned mask is xored with `neg`, so a
@@ -818,16 +892,49 @@ __device__ __forceinline__ void half_sweep_lds(const LdsRep<L>& rep, int gl, uin
 #pragma unroll 1
     for (int k0 = 0; k0 < Gm::K; k0 += S) {
         uint32_t tie[S], k2[S], ng[S], extra[S];
+        if constexpr (HB) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int k = k0 + s;
-            const Nb n = rep.template nb<C>(k, gl);
-            uint32_t& own = rep.at(C, k, gl);
-            if constexpr (HB) {
+            for (int s = 0; s < S; ++s) {
+                const int k = k0 + s;
+                const Nb n = rep.template nb<C>(k, gl);
+                uint32_t& own = rep.at(C, k, gl);
                 own ^= decide8_hb(own, n, (uint32_t)(gl * Gm::K + k), ctr1, j, a, tie[s], k2[s], ng[s]);
-            } else {
+            }
+        } else if constexpr (S == 4) {
+            // L = 128: the branch-free chains per word; grouping the four words
+            // needs more registers and costs a wave per SIMD (measured slower)
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int k = k0 + s;
+                const Nb n = rep.template nb<C>(k, gl);
+                uint32_t& own = rep.at(C, k, gl);
                 own ^= decide8(own, n, (uint32_t)(gl * Gm::K + k), ctr1, j, a, tie[s], k2[s]);
                 ng[s] = 0u;
+            }
+        } else {
+            // L = 256 (eight slots): groups of four words share the per-plane
+            // branches of decide8_group
+            constexpr int NG = 4;
+            static_assert(S % NG == 0, "slot groups");
+#pragma unroll
+            for (int s0 = 0; s0 < S; s0 += NG) {
+                uint32_t w[NG], v[NG], tg[NG], cg[NG];
+                Nb n[NG];
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    const int k = k0 + s0 + g;
+                    n[g] = rep.template nb<C>(k, gl);
+                    w[g] = rep.at(C, k, gl);
+                    v[g] = (uint32_t)(gl * Gm::K + k);
+                }
+                decide8_group<NG>(w, n, v, ctr1, j, a, tg, cg);
+#pragma unroll
+                for (int g = 0; g < NG; ++g) {
+                    rep.at(C, k0 + s0 + g, gl) = w[g];
+                    tie[s0 + g] = tg[g];
+                    k2[s0 + g] = cg[g];
+                    ng[s0 + g] = 0u;
+                }
             }
         }
         const auto vj = [&](int owner, int s, uint32_t* vo, uint32_t* jo) {
