@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void b_copy(const Item* __restrict__ items,
 
 // Item blk covers waves [blk * wpb, (blk + 1) * wpb) of the run (wpb = blockDim.x / 64).
 template <int L, bool INT8, bool HB>
-__global__ __launch_bounds__(512) void b_sweep(const Item* __restrict__ items, const RunDev* __restrict__ runs,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<L>(), 8))) void b_sweep(const Item* __restrict__ items, const RunDev* __restrict__ runs,
                                                const StepDev* __restrict__ steps, const ResultDev* __restrict__ res)
 {
     extern __shared__ uint32_t lds_dyn[];

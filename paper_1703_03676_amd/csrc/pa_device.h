@@ -900,20 +900,9 @@ __device__ __forceinline__ void half_sweep_lds(const LdsRep<L>& rep, int gl, uin
                 uint32_t& own = rep.at(C, k, gl);
                 own ^= decide8_hb(own, n, (uint32_t)(gl * Gm::K + k), ctr1, j, a, tie[s], k2[s], ng[s]);
             }
-        } else if constexpr (S == 4) {
-            // L = 128: the branch-free chains per word; grouping the four words
-            // needs more registers and costs a wave per SIMD (measured slower)
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const int k = k0 + s;
-                const Nb n = rep.template nb<C>(k, gl);
-                uint32_t& own = rep.at(C, k, gl);
-                own ^= decide8(own, n, (uint32_t)(gl * Gm::K + k), ctr1, j, a, tie[s], k2[s]);
-                ng[s] = 0u;
-            }
         } else {
-            // L = 256 (eight slots): groups of four words share the per-plane
-            // branches of decide8_group
+            // groups of four words share the per-plane branches of
+            // decide8_group (L = 128: one group, L = 256: two)
             constexpr int NG = 4;
             static_assert(S % NG == 0, "slot groups");
 #pragma unroll
@@ -995,6 +984,16 @@ __device__ __forceinline__ void sweep_lds(const SweepArgs& a, uint32_t j, uint32
     li.j = j;
     li.valid = true;
     write_EM<L>(a, li, anti, downs);
+}
+
+// Minimum waves per SIMD the sweep kernels are compiled for.  At L = 128 the
+// grouped decision needs a few more registers than fit three waves per SIMD;
+// holding the kernel to three (a few values go to scratch outside the inner
+// loops) is faster than two waves without the cap.
+template <int L>
+constexpr int sweep_min_waves()
+{
+    return L == 128 ? 3 : 1;
 }
 
 // Threads per block of the single-run sweep kernel.

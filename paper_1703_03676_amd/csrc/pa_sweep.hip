@@ -24,7 +24,8 @@ namespace {
 using namespace pa::dev;
 
 template <int L, bool INT8, bool HB>
-__global__ __launch_bounds__(sweep_block<L>()) void sweep_kernel(SweepArgs a)
+__global__ __launch_bounds__(sweep_block<L>())
+__attribute__((amdgpu_waves_per_eu(sweep_min_waves<L>(), 8))) void sweep_kernel(SweepArgs a)
 {
     using Gm = Geo<L>;
     constexpr int WPB = sweep_block<L>() / 64;
