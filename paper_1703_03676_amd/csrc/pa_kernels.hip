@@ -110,36 +110,69 @@ __global__ __launch_bounds__(kBlock) void counts_kernel(const int32_t* __restric
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
+// Single block: exclusive scan of the block totals in place; the grand total
+// goes to st->r_new.  Used when there are more than kScanFreeBlocks blocks.
+__global__ __launch_bounds__(1024) void scan_blocks_kernel(uint32_t* bsum, int32_t nblk, DevStats* st)
+{
+    __shared__ uint32_t part[1024];
+    const int t = (int)threadIdx.x;
+    const int per = (nblk + 1023) / 1024;
+    const int lo = t * per, hi = min(nblk, lo + per);
+    uint32_t s = 0;
+    for (int i = lo; i < hi; ++i) s += bsum[i];
+    part[t] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t y = (t >= off) ? part[t - off] : 0u;
+        __syncthreads();
+        part[t] += y;
+        __syncthreads();
+    }
+    uint32_t run = part[t] - s;  // exclusive prefix of this thread's chunk
+    for (int i = lo; i < hi; ++i) {
+        const uint32_t v = bsum[i];
+        bsum[i] = run;
+        run += v;
+    }
+    if (t == 1023) st->r_new = part[1023];
+}
+
 // Parent index of every child; children beyond `cap` are not written (the
-// caller rejects such a population).  The offset of the block's first child is
-// the sum of the totals of the blocks before it (bsum, from counts_kernel), so
-// no separate scan pass is needed; the last block writes the grand total to
-// st->r_new.  The kernel also clears the rest of the statistics block and the
-// histogram, ready for the statistics of the resampled population (the host
-// has read the previous ones).
+// caller rejects such a population).  Without `scanned`, the offset of the
+// block's first child is the sum of the totals of the blocks before it (bsum,
+// from counts_kernel), so no separate scan pass is needed, and the last block
+// writes the grand total to st->r_new; with `scanned`, bsum already holds the
+// exclusive prefix (scan_blocks_kernel, for many blocks, where summing would
+// grow with the square of their number).  The kernel also clears the rest of
+// the statistics block and the histogram, ready for the statistics of the
+// resampled population (the host has read the previous ones).
 __global__ __launch_bounds__(kBlock) void scatter_kernel(const uint32_t* __restrict__ counts,
                                                          const uint32_t* __restrict__ bsum, int32_t n, uint32_t cap,
                                                          uint32_t* __restrict__ parent, DevStats* st,
-                                                         uint32_t* __restrict__ hist, int32_t nbins)
+                                                         uint32_t* __restrict__ hist, int32_t nbins, int scanned)
 {
     __shared__ uint32_t wpart[kBlock / 64];
     const int lane = (int)(threadIdx.x & 63u), wid = (int)(threadIdx.x >> 6);
-    uint32_t before = 0;
-    for (int i = (int)threadIdx.x; i < (int)blockIdx.x; i += kBlock) before += bsum[i];
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) before += (uint32_t)__shfl_xor((int)before, off);
-    if (lane == 0) wpart[wid] = before;
-    __syncthreads();
     uint32_t base = 0;
+    if (scanned) {
+        base = bsum[blockIdx.x];
+    } else {
+        uint32_t before = 0;
+        for (int i = (int)threadIdx.x; i < (int)blockIdx.x; i += kBlock) before += bsum[i];
 #pragma unroll
-    for (int w = 0; w < kBlock / 64; ++w) base += wpart[w];
+        for (int off = 32; off >= 1; off >>= 1) before += (uint32_t)__shfl_xor((int)before, off);
+        if (lane == 0) wpart[wid] = before;
+        __syncthreads();
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) base += wpart[w];
+    }
     const int j = (int)(blockIdx.x * kBlock + threadIdx.x);
     const uint32_t c = (j < n) ? counts[j] : 0u;
     uint32_t total;
     const uint32_t off = base + block_exclusive_scan(c, &total);
     for (uint32_t k = 0; k < c && off + k < cap; ++k) parent[off + k] = (uint32_t)j;
     if (threadIdx.x == 0) {
-        if (blockIdx.x == gridDim.x - 1) st->r_new = base + total;
+        if (!scanned && blockIdx.x == gridDim.x - 1) st->r_new = base + total;
         if (blockIdx.x == 0) {
             st->emin = 0x7FFFFFFF;
             st->emax = (int32_t)0x80000000;
@@ -233,12 +266,14 @@ hipError_t launch_counts(const int32_t* E, int32_t n, int32_t N, int32_t bmin, i
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(const uint32_t* counts, const uint32_t* bsum, int32_t n, int32_t cap, uint32_t* parent,
+hipError_t launch_scatter(const uint32_t* counts, uint32_t* bsum, int32_t n, int32_t cap, uint32_t* parent,
                           DevStats* st, uint32_t* hist, int32_t nbins, hipStream_t s)
 {
     const int blocks = std::max((n + kBlock - 1) / kBlock, 1);
-    hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(kBlock), 0, s, counts, bsum, n, (uint32_t)cap, parent, st,
-                       hist, nbins);
+    const int scanned = blocks > kScanFreeBlocks ? 1 : 0;
+    if (scanned) hipLaunchKernelGGL(scan_blocks_kernel, dim3(1), dim3(1024), 0, s, bsum, blocks, st);
+    hipLaunchKernelGGL(scatter_kernel, dim3(blocks), dim3(kBlock), 0, s, counts, (const uint32_t*)bsum, n,
+                       (uint32_t)cap, parent, st, hist, nbins, scanned);
     return hipGetLastError();
 }
 

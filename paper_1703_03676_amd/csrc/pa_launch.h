@@ -26,7 +26,10 @@ hipError_t launch_counts(const int32_t* E, int32_t n, int32_t N, int32_t bmin, i
 // st->r_new, and the statistics block and histogram cleared for the next
 // statistics; then the replica copy of min(*n_new, cap) children, n_new read
 // on the device.
-hipError_t launch_scatter(const uint32_t* counts, const uint32_t* bsum, int32_t n, int32_t cap, uint32_t* parent,
+// Up to kScanFreeBlocks blocks of counts, each scatter block sums the totals
+// before it; beyond, a single-block scan of the totals runs first.
+constexpr int kScanFreeBlocks = 1024;
+hipError_t launch_scatter(const uint32_t* counts, uint32_t* bsum, int32_t n, int32_t cap, uint32_t* parent,
                           DevStats* st, uint32_t* hist, int32_t nbins, hipStream_t s);
 hipError_t launch_copy(const uint8_t* src, const int32_t* Esrc, const int32_t* Msrc, const uint32_t* parent,
                        const uint32_t* n_new, int32_t cap, size_t rep_bytes, uint8_t* dst, int32_t* Edst,

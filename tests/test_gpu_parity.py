@@ -118,6 +118,23 @@ def test_resample_matches_oracle(L, layout):
         assert st["lnZ"] == o.lnZ and st["step"] == o.step and st["beta"] == o.beta
 
 
+def test_resample_many_blocks_uses_the_block_scan():
+    """More than 1024 blocks of 256 parents: the scatter takes the block totals
+    from a single-block scan instead of summing them itself; counts, R_i,
+    parents (through the copied population) and the statistics that follow
+    match the oracle."""
+    L, R = 16, 300000
+    print("case resample many blocks L=%d R=%d" % (L, R), flush=True)
+    g = pa.Run(L, R, seed=5, layout="bits")
+    o = oracle.Run(L, R, seed=5)
+    o.init()
+    gi, oi = g.resample(0.35), o.resample(0.35)
+    assert gi == oi
+    assert np.array_equal(g.download_counts(g.capacity), o.get_counts())
+    _same_population(g, o)
+    _same_obs(g.observables(), o.measure())
+
+
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("L,R,kind", [(64, 600, "ordered"), (64, 600, "mixed"), (128, 300, "mixed")])
 def test_statistics_windows_and_multi_histogram(L, R, kind, layout):
