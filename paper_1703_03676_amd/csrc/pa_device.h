@@ -421,72 +421,48 @@ __device__ __forceinline__ void half_sweep(uint32_t (&own)[Geo<L>::K], const uin
 }
 
 
-// Decisions of the first 8 bit planes (Philox blocks 0 and 1) for the 32
-// sites of a word.  A site flips if at least two of its four neighbours are
+// Decisions of the first 8 bit planes (Philox blocks 0 and 1) for NG words of
+// one lane together.  A site flips if at least two of its four neighbours are
 // anti-aligned (k = s h <= 0); a site with one anti-aligned neighbour (k = 2,
 // `cls1`) or none (k = 4) flips if its uniform x is below T_2 or T_4.  The
-// high 8 bits of x are compared with those of T as an 8-bit subtraction, least
-// significant plane first: the borrow b' = maj(~x, b, t) of the last plane is
-// "x < T", and e tracks equality.  The threshold bits are uniform masks (0 or
-// ~0), so every plane is four branch-free bit operations for both classes.
-// Returns the sites accepted; `tie` receives the sites whose 8 high bits equal
-// the threshold's (probability 2^-8 each), decided later by decide_tail.
-__device__ __forceinline__ uint32_t decide8(uint32_t w, const Nb& n, uint32_t v, uint32_t ctr1, uint32_t j,
-                                            const SweepArgs& a, uint32_t& tie, uint32_t& cls1)
-{
-    const uint32_t d1 = w ^ n.up, d2 = w ^ n.dn, d3 = w ^ n.same, d4 = w ^ n.side;
-    const uint32_t o12 = d1 | d2, a12 = d1 & d2, o34 = d3 | d4, a34 = d3 & d4;
-    const uint32_t ge2 = a12 | a34 | (o12 & o34);
-    const uint32_t any = o12 | o34;
-    cls1 = any & ~ge2;                                     // k = 2
-    const uint32_t cls2 = ~any;                            // k = 4
-    const uint32_t all2 = (a.t2h > 0xFFFFu) ? cls1 : 0u;   // T = 2^32: always accepted
-    const uint32_t all4 = (a.t4h > 0xFFFFu) ? cls2 : 0u;
-    const uint32_t u2 = cls1 & ~all2, u4 = cls2 & ~all4;   // sites that need their uniform
-    uint32_t acc = ge2 | all2 | all4;
-    tie = 0u;
-    if (!__any((u2 | u4) != 0u)) return acc;
-    const U4 P0 = philox10u(4u * v, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
-    const U4 P1 = philox10u(4u * v + 1u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
-    const uint32_t pl[8] = {P0.x, P0.y, P0.z, P0.w, P1.x, P1.y, P1.z, P1.w};
-    uint32_t b2 = 0u, b4 = 0u, e2 = ~0u, e4 = ~0u;
-#pragma unroll
-    for (int p = 7; p >= 0; --p) {
-        const uint32_t m2 = 0u - ((a.t2h >> (15 - p)) & 1u);
-        const uint32_t m4 = 0u - ((a.t4h >> (15 - p)) & 1u);
-        b2 = __builtin_amdgcn_bitop3_b32(pl[p], b2, m2, 0x8E);  // maj(~x, b, t)
-        b4 = __builtin_amdgcn_bitop3_b32(pl[p], b4, m4, 0x8E);
-        e2 = __builtin_amdgcn_bitop3_b32(e2, pl[p], m2, 0x90);  // e & ~(x ^ t)
-        e4 = __builtin_amdgcn_bitop3_b32(e4, pl[p], m4, 0x90);
-    }
-    acc |= (u2 & b2) | (u4 & b4);
-    tie = (u2 & e2) | (u4 & e4);
-    return acc;
-}
-
-// decide8 for NG words of one lane together: the 8 planes are compared high
-// bit first with one uniform branch per plane over the two threshold bits,
-// shared by the NG words (2-3 operations per word and plane, instead of the 4
-// of the two branch-free chains).  Same acceptances and ties as decide8.
-template <int NG>
+// planes are compared high bit first with one uniform branch per plane over the
+// two threshold bits, shared by the NG words: 2-3 operations per word and
+// plane.  The words are updated with their decided flips; `tie` receives the
+// sites whose 8 high bits equal the threshold's (probability 2^-8 each),
+// decided later by decide_tail.  With HB (heat-bath, the update of
+// heatbath_mask) every site draws, the k = 0 sites are decided by plane 0, the
+// k < 0 sites compare the complemented planes (`ng`) and are flipped
+// provisionally, so that the tail's result xored on top gives their decision.
+template <int NG, bool HB>
 __device__ __forceinline__ void decide8_group(uint32_t (&w)[NG], const Nb (&n)[NG], const uint32_t (&v)[NG],
                                               uint32_t ctr1, uint32_t j, const SweepArgs& a, uint32_t (&tie)[NG],
-                                              uint32_t (&cls1)[NG])
+                                              uint32_t (&cls1)[NG], uint32_t (&ng)[NG])
 {
-    uint32_t eq[NG], acc[NG];
+    uint32_t eq[NG], acc[NG], zero[NG];
     uint32_t need = 0u;
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
-        const uint32_t d1 = w[g] ^ n[g].up, d2 = w[g] ^ n[g].dn, d3 = w[g] ^ n[g].same, d4 = w[g] ^ n[g].side;
-        const uint32_t o12 = d1 | d2, a12 = d1 & d2, o34 = d3 | d4, a34 = d3 & d4;
-        const uint32_t ge2 = a12 | a34 | (o12 & o34);
-        const uint32_t any = o12 | o34;
-        cls1[g] = any & ~ge2;
-        const uint32_t cls2 = ~any;
-        const uint32_t all2 = (a.t2h > 0xFFFFu) ? cls1[g] : 0u;
-        const uint32_t all4 = (a.t4h > 0xFFFFu) ? cls2 : 0u;
-        eq[g] = (cls1[g] & ~all2) | (cls2 & ~all4);
-        acc[g] = ge2 | all2 | all4;
+        if constexpr (HB) {
+            const HbClass c = hb_classes(w[g], n[g]);
+            cls1[g] = c.cls1;
+            ng[g] = c.neg;
+            zero[g] = c.zero;
+            eq[g] = ~c.zero;
+            acc[g] = 0u;
+        } else {
+            const uint32_t d1 = w[g] ^ n[g].up, d2 = w[g] ^ n[g].dn, d3 = w[g] ^ n[g].same, d4 = w[g] ^ n[g].side;
+            const uint32_t o12 = d1 | d2, a12 = d1 & d2, o34 = d3 | d4, a34 = d3 & d4;
+            const uint32_t ge2 = a12 | a34 | (o12 & o34);
+            const uint32_t any = o12 | o34;
+            cls1[g] = any & ~ge2;
+            const uint32_t cls2 = ~any;
+            const uint32_t all2 = (a.t2h > 0xFFFFu) ? cls1[g] : 0u;  // T = 2^32: always accepted
+            const uint32_t all4 = (a.t4h > 0xFFFFu) ? cls2 : 0u;
+            eq[g] = (cls1[g] & ~all2) | (cls2 & ~all4);
+            acc[g] = ge2 | all2 | all4;
+            ng[g] = 0u;
+            zero[g] = 0u;
+        }
         need |= eq[g];
     }
     if (__any(need != 0u)) {
@@ -497,6 +473,11 @@ __device__ __forceinline__ void decide8_group(uint32_t (&w)[NG], const Nb (&n)[N
             const U4 P1 = philox10u(4u * v[g] + 1u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
             pl[g][0] = P0.x, pl[g][1] = P0.y, pl[g][2] = P0.z, pl[g][3] = P0.w;
             pl[g][4] = P1.x, pl[g][5] = P1.y, pl[g][6] = P1.z, pl[g][7] = P1.w;
+            if constexpr (HB) {
+                acc[g] = zero[g] & ~pl[g][0];  // U_0 = 2^31: x < U_0 iff its top bit is 0
+#pragma unroll
+                for (int q = 0; q < 8; ++q) pl[g][q] ^= ng[g];
+            }
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
@@ -533,40 +514,9 @@ __device__ __forceinline__ void decide8_group(uint32_t (&w)[NG], const Nb (&n)[N
     }
 #pragma unroll
     for (int g = 0; g < NG; ++g) {
-        w[g] ^= acc[g];
+        w[g] ^= acc[g] ^ ng[g];
         tie[g] = eq[g];
     }
-}
-
-// Heat-bath form of decide8 (the update of heatbath_mask): the planes of the
-// k < 0 sites are complemented before the comparison with U_|k|, the k = 0
-// sites are decided by plane 0, and the returned mask is xored with `neg`, so a
-// k < 0 site still tied is provisionally flipped and the tail's result (the
-// comparison of the complemented uniform) xored on top gives its decision.
-__device__ __forceinline__ uint32_t decide8_hb(uint32_t w, const Nb& n, uint32_t v, uint32_t ctr1, uint32_t j,
-                                               const SweepArgs& a, uint32_t& tie, uint32_t& cls1, uint32_t& neg)
-{
-    const HbClass c = hb_classes(w, n);
-    cls1 = c.cls1;
-    neg = c.neg;
-    const uint32_t cls2 = ~(c.zero | c.cls1);  // |k| = 4
-    const U4 P0 = philox10u(4u * v, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
-    const U4 P1 = philox10u(4u * v + 1u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
-    const uint32_t pl[8] = {P0.x, P0.y, P0.z, P0.w, P1.x, P1.y, P1.z, P1.w};
-    uint32_t b2 = 0u, b4 = 0u, e2 = ~0u, e4 = ~0u;
-#pragma unroll
-    for (int p = 7; p >= 0; --p) {
-        const uint32_t y = pl[p] ^ c.neg;
-        const uint32_t m2 = 0u - ((a.t2h >> (15 - p)) & 1u);
-        const uint32_t m4 = 0u - ((a.t4h >> (15 - p)) & 1u);
-        b2 = __builtin_amdgcn_bitop3_b32(y, b2, m2, 0x8E);  // maj(~y, b, t)
-        b4 = __builtin_amdgcn_bitop3_b32(y, b4, m4, 0x8E);
-        e2 = __builtin_amdgcn_bitop3_b32(e2, y, m2, 0x90);  // e & ~(y ^ t)
-        e4 = __builtin_amdgcn_bitop3_b32(e4, y, m4, 0x90);
-    }
-    const uint32_t acc = (c.zero & ~pl[0]) | (c.cls1 & b2) | (cls2 & b4);
-    tie = (c.cls1 & e2) | (cls2 & e4);
-    return acc ^ c.neg;
 }
 
 // Remaining comparison of site b of word v, tied after 8 planes: planes 8..15
@@ -615,7 +565,7 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Tie queue of one wave.  The sites still tied after decide8 are rare (2^-8
+// Tie queue of one wave.  The sites still tied after decide8_group are rare (2^-8
 // each), so instead of evaluating the later Philox blocks for every word, the
 // tied sites of the S words of every lane are queued in LDS and decided one per
 // lane.  An entry is  bits 0-4 site | bit 5 class k = 2 | bits 6-11 lane |
@@ -892,38 +842,28 @@ __device__ __forceinline__ void half_sweep_lds(const LdsRep<L>& rep, int gl, uin
 #pragma unroll 1
     for (int k0 = 0; k0 < Gm::K; k0 += S) {
         uint32_t tie[S], k2[S], ng[S], extra[S];
-        if constexpr (HB) {
+        // groups of four words share the per-plane branches of decide8_group
+        // (L = 128: one group, L = 256: two)
+        constexpr int NG = 4;
+        static_assert(S % NG == 0, "slot groups");
 #pragma unroll
-            for (int s = 0; s < S; ++s) {
-                const int k = k0 + s;
-                const Nb n = rep.template nb<C>(k, gl);
-                uint32_t& own = rep.at(C, k, gl);
-                own ^= decide8_hb(own, n, (uint32_t)(gl * Gm::K + k), ctr1, j, a, tie[s], k2[s], ng[s]);
+        for (int s0 = 0; s0 < S; s0 += NG) {
+            uint32_t w[NG], v[NG], tg[NG], cg[NG], ngg[NG];
+            Nb n[NG];
+#pragma unroll
+            for (int g = 0; g < NG; ++g) {
+                const int k = k0 + s0 + g;
+                n[g] = rep.template nb<C>(k, gl);
+                w[g] = rep.at(C, k, gl);
+                v[g] = (uint32_t)(gl * Gm::K + k);
             }
-        } else {
-            // groups of four words share the per-plane branches of
-            // decide8_group (L = 128: one group, L = 256: two)
-            constexpr int NG = 4;
-            static_assert(S % NG == 0, "slot groups");
+            decide8_group<NG, HB>(w, n, v, ctr1, j, a, tg, cg, ngg);
 #pragma unroll
-            for (int s0 = 0; s0 < S; s0 += NG) {
-                uint32_t w[NG], v[NG], tg[NG], cg[NG];
-                Nb n[NG];
-#pragma unroll
-                for (int g = 0; g < NG; ++g) {
-                    const int k = k0 + s0 + g;
-                    n[g] = rep.template nb<C>(k, gl);
-                    w[g] = rep.at(C, k, gl);
-                    v[g] = (uint32_t)(gl * Gm::K + k);
-                }
-                decide8_group<NG>(w, n, v, ctr1, j, a, tg, cg);
-#pragma unroll
-                for (int g = 0; g < NG; ++g) {
-                    rep.at(C, k0 + s0 + g, gl) = w[g];
-                    tie[s0 + g] = tg[g];
-                    k2[s0 + g] = cg[g];
-                    ng[s0 + g] = 0u;
-                }
+            for (int g = 0; g < NG; ++g) {
+                rep.at(C, k0 + s0 + g, gl) = w[g];
+                tie[s0 + g] = tg[g];
+                k2[s0 + g] = cg[g];
+                ng[s0 + g] = ngg[g];
             }
         }
         const auto vj = [&](int owner, int s, uint32_t* vo, uint32_t* jo) {
