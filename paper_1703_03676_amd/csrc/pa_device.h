@@ -57,7 +57,7 @@ __device__ __forceinline__ U4 philox10u(uint32_t c0, uint32_t c1, uint32_t c2, u
 {
     uint64_t p0, p1;
     uint32_t n0, n2;
-    // round 1: c1, c2, c3 uniform
+    // first Philox round: c1, c2, c3 uniform
     p0 = (uint64_t)kM0 * c0;
     p1 = (uint64_t)kM1 * c2;
     n0 = ((uint32_t)(p1 >> 32) ^ c1) ^ k0;
@@ -68,7 +68,7 @@ __device__ __forceinline__ U4 philox10u(uint32_t c0, uint32_t c1, uint32_t c2, u
     c2 = n2;
     k0 += kW0;
     k1 += kW1;
-    // round 2: c0, c1 uniform
+    // second Philox round: c0, c1 uniform
     p0 = (uint64_t)kM0 * c0;
     p1 = (uint64_t)kM1 * c2;
     n0 = (uint32_t)(p1 >> 32) ^ (c1 ^ k0);
@@ -79,7 +79,7 @@ __device__ __forceinline__ U4 philox10u(uint32_t c0, uint32_t c1, uint32_t c2, u
     c2 = n2;
     k0 += kW0;
     k1 += kW1;
-    // round 3: c3 uniform
+    // third Philox round: c3 uniform
     p0 = (uint64_t)kM0 * c0;
     p1 = (uint64_t)kM1 * c2;
     n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
