@@ -288,19 +288,21 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_
         }
     }
     if (__any(eq != 0u)) {
-        // blocks 0 and 1 are computed together (two independent chains), since
-        // the first four planes leave some site of the wave tied almost surely
+        // blocks 0, 1 and 2 are computed together (three independent chains),
+        // since the first eight planes leave some site of the wave tied almost
+        // surely (the wave holds about 2000 sites that need a uniform)
         const U4 P0 = philox10(4u * v, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
         const U4 P1 = philox10(4u * v + 1u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
-        const uint32_t pl[8] = {P0.x, P0.y, P0.z, P0.w, P1.x, P1.y, P1.z, P1.w};
+        const U4 P2 = philox10(4u * v + 2u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+        const uint32_t pl[12] = {P0.x, P0.y, P0.z, P0.w, P1.x, P1.y, P1.z, P1.w, P2.x, P2.y, P2.z, P2.w};
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < 12; ++q) {
             const int bit = 15 - q;
             const uint32_t tb = (((a.t2h >> bit) & 1u) << 1) | ((a.t4h >> bit) & 1u);
             compare_plane(pl[q], tb, cls1, eq, acc);
         }
 #pragma unroll
-        for (int kk = 2; kk < 4; ++kk) {
+        for (int kk = 3; kk < 4; ++kk) {
             if (!__any(eq != 0u)) break;
             const U4 P = philox10(4u * v + (uint32_t)kk, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
             const uint32_t pq[4] = {P.x, P.y, P.z, P.w};
@@ -363,19 +365,20 @@ __device__ __forceinline__ uint32_t heatbath_mask(uint32_t w, const Nb& n, uint3
 {
     const HbClass c = hb_classes(w, n);
     uint32_t eq = ~c.zero;
-    // blocks 0 and 1 together (two independent chains), as in accept_mask
+    // blocks 0, 1 and 2 together (three independent chains), as in accept_mask
     const U4 P0 = philox10(4u * v, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
     const U4 P1 = philox10(4u * v + 1u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
-    const uint32_t pl[8] = {P0.x, P0.y, P0.z, P0.w, P1.x, P1.y, P1.z, P1.w};
+    const U4 P2 = philox10(4u * v + 2u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+    const uint32_t pl[12] = {P0.x, P0.y, P0.z, P0.w, P1.x, P1.y, P1.z, P1.w, P2.x, P2.y, P2.z, P2.w};
     uint32_t acc = c.zero & ~pl[0];  // U_0 = 2^31: x < U_0 iff its top bit is 0
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
+    for (int q = 0; q < 12; ++q) {
         const int bit = 15 - q;
         const uint32_t tb = (((a.t2h >> bit) & 1u) << 1) | ((a.t4h >> bit) & 1u);
         compare_plane(pl[q] ^ c.neg, tb, c.cls1, eq, acc);
     }
 #pragma unroll
-    for (int kk = 2; kk < 4; ++kk) {
+    for (int kk = 3; kk < 4; ++kk) {
         if (!__any(eq != 0u)) break;
         const U4 P = philox10(4u * v + (uint32_t)kk, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
         const uint32_t pq[4] = {P.x, P.y, P.z, P.w};
