@@ -55,12 +55,17 @@ __global__ __launch_bounds__(kBlock) void stats_kernel(const int32_t* __restrict
         if (blockIdx.x == 0) stats_publish(parts, 0, st, hist, N, host);
         return;
     }
-    const int32_t i0 = (int32_t)(blockIdx.x * kBlock);
-    if (i0 >= n) return;  // uniform per block
-    stats_block(E, M, n, N, i0, hist, nbins, record != 0, mhr, &parts[blockIdx.x]);
-    __threadfence();  // this block's partial and histogram updates, device-wide
+    // chunks of kBlock replicas, strided over the grid; the blocks that hold
+    // at least one chunk count themselves in st->done
+    const int nblk = min(nparts, (int)gridDim.x);
+    if ((int)blockIdx.x >= nblk) return;  // uniform per block
+    for (int c = (int)blockIdx.x; c < nparts; c += (int)gridDim.x) {
+        stats_block(E, M, n, N, c * kBlock, hist, nbins, record != 0, mhr, &parts[c]);
+        __syncthreads();  // the LDS tables are reused by the next chunk
+    }
+    __threadfence();  // this block's partials and histogram updates, device-wide
     __syncthreads();
-    if (threadIdx.x == 0) last = (atomicAdd(&st->done, 1u) == (uint32_t)(nparts - 1)) ? 1u : 0u;
+    if (threadIdx.x == 0) last = (atomicAdd(&st->done, 1u) == (uint32_t)(nblk - 1)) ? 1u : 0u;
     __syncthreads();
     if (!last) return;  // uniform per block
     __threadfence();    // every other block's updates are visible to this one
@@ -234,7 +239,9 @@ hipError_t launch_stats(const int32_t* E, const int32_t* M, int32_t n, const uin
                         DevStats* st, uint32_t* hist, int32_t nbins, int record, DevMhr mhr, StatsPart* parts,
                         void* host, hipStream_t s)
 {
-    const int blocks = (n + kBlock - 1) / kBlock;
+    // at most kStatsBlocks blocks: each block's device-wide fence before it is
+    // counted costs more than the chunks it saves beyond that
+    const int blocks = std::min((n + kBlock - 1) / kBlock, kStatsBlocks);
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(stats_kernel, dim3(blocks), dim3(kBlock), 0, s, E, M, n, n_dev, N, hist, nbins, record, mhr,
                        parts, st, (uint32_t*)host);

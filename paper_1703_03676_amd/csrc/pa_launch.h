@@ -12,7 +12,9 @@ hipError_t launch_sweep(int L, int layout, bool heatbath, const SweepArgs& a, hi
 // Statistics of a population (after the statistics block and the histogram
 // have been cleared, by launch_stats_reset or launch_scatter): histogram,
 // range, moment sums; parts holds ceil(n / kBlock) partials.  With n_dev the
-// size is min(*n_dev, n), read on the device.
+// size is min(*n_dev, n), read on the device.  At most kStatsBlocks blocks,
+// each taking chunks of kBlock replicas in turn.
+constexpr int kStatsBlocks = 128;
 hipError_t launch_stats(const int32_t* E, const int32_t* M, int32_t n, const uint32_t* n_dev, int32_t N,
                         DevStats* st, uint32_t* hist, int32_t nbins, int record, DevMhr mhr, StatsPart* parts,
                         void* host, hipStream_t s);
