@@ -163,6 +163,35 @@ def test_statistics_windows_and_multi_histogram(L, R, kind, layout):
             assert _close(go[k], oo[k], 1e-12), (k, go["beta"], go[k], oo[k])
 
 
+@pytest.mark.parametrize("kind", ["ordered", "mixed"])
+def test_statistics_more_chunks_than_workgroups(kind):
+    """The statistics kernel runs a bounded number of workgroups that take
+    256-replica chunks in turn: R = 40000 gives 157 chunks, more than the
+    workgroups, with a ragged last chunk.  Statistics, the multi-histogram
+    accumulators and the reweighted observables match the oracle."""
+    L, R = 16, 40000
+    print("case stats chunks L=%d R=%d %s" % (L, R, kind), flush=True)
+    if kind == "ordered":
+        spins = inputs.ordered_spins(R, L, seed=31, n_flipped_max=30)
+    else:
+        spins = inputs.mixed_spins(R, L, seed=32)
+    g = pa.Run(L, R, seed=17, layout="bits", mhr=True)
+    o = oracle.Run(L, R, seed=17)
+    g.upload_population(spins, step=2, sweeps=5, beta=0.35, lnZ=3.0)
+    o.set_population(spins, step=2, sweeps=5, beta=0.35, lnZ=3.0)
+    _same_obs(g.observables(), o.measure())
+    for beta in (0.36, 0.4):
+        assert g.resample(beta) == o.resample(beta)
+        g.sweep(1)
+        o.sweep(1)
+        _same_obs(g.observables(), o.measure())
+    _same_population(g, o)
+    betas = np.linspace(0.3, 0.5, 11)
+    for go, oo in zip(g.reweight(betas), o.reweight(betas)):
+        for k in ("e", "C", "abs_m", "m2", "m4", "betaF_per_N", "S_per_N"):
+            assert _close(go[k], oo[k], 1e-12), (k, go["beta"], go[k], oo[k])
+
+
 def _l16_trace(run, nsteps, theta, dbeta, measure):
     trace = [measure()]
     for i in range(1, nsteps + 1):
