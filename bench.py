@@ -472,7 +472,7 @@ def main():
                     help="l64 (default) is the headline workload; the others print their own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(population annealing would shard by replica, one population share per GPU)", file=sys.stderr)
         return 2
 

@@ -62,7 +62,7 @@ enum {
 };
 
 typedef struct {
-    int32_t L;          /* lattice edge; this build runs L in {16, 32, 64, 128, 256} */
+    int32_t L;          /* lattice edge; the library runs L in {16, 32, 64, 128, 256} */
     int32_t R;          /* target population size R (Sec. 2.1), >= 1 */
     int32_t capacity;   /* maximum population; 0 selects R + ceil(10 sqrt(R)) + 64 */
     int32_t layout;     /* pa_layout of the spin store */
