@@ -267,6 +267,83 @@ def test_anneal_adaptive_with_reweighting(layout):
             assert _close(go[k], oo[k], 1e-12), (k, go["beta"], go[k], oo[k])
 
 
+def _fixed_betas(step0, beta0, beta_f, dbeta):
+    """Inverse temperatures of a fixed schedule after step step0 (the host's
+    rule: i * dbeta, beta_f from step round(beta_f / dbeta) on)."""
+    nb = max(1, round(beta_f / dbeta))
+    out, i, b = [], step0, beta0
+    while b < beta_f:
+        i += 1
+        b = max(beta_f if i >= nb else min(i * dbeta, beta_f), b)
+        out.append(b)
+    return out
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_anneal_refusal_in_the_middle_of_a_run(layout):
+    """A step refused for capacity after other steps of the same pa_anneal
+    call leaves the run at the last completed step, equal to the oracle's;
+    runs that are not refused match the oracle at every step."""
+    print("case anneal refusal mid-run layout=%s" % layout, flush=True)
+    refused_late = 0
+    for seed in range(1, 31):
+        g = pa.Run(16, 100, seed=seed, capacity=100, layout=layout)
+        o = oracle.Run(16, 100, seed=seed, capacity=100)
+        s = np.ones((3, 16, 16), np.int8)
+        g.upload_population(s, step=1, beta=0.1)
+        o.set_population(s, step=1, beta=0.1)
+        trace, refused_at = [], None
+        for k, b in enumerate(_fixed_betas(1, 0.1, 0.6, 0.1)):
+            try:
+                o.resample(b)
+            except OverflowError:
+                refused_at = k
+                break
+            o.sweep(2)
+            trace.append(o.measure())
+        if refused_at is None:
+            obs = g.anneal(beta_f=0.6, dbeta=0.1, theta=2)
+            assert len(obs) == len(trace)
+            for go, oo in zip(obs, trace):
+                _same_obs(go, oo)
+        else:
+            refused_late += refused_at > 0
+            with pytest.raises(pa.CapacityError):
+                g.anneal(beta_f=0.6, dbeta=0.1, theta=2)
+            st = g.state()
+            assert st["step"] == 1 + refused_at and st["sweeps"] == 2 * refused_at
+            _same_obs(g.observables(), o.measure())
+        _same_population(g, o)
+        g.sweep(1)
+        o.sweep(1)
+        _same_population(g, o)
+    assert refused_late > 0
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+def test_anneal_from_an_ordered_population(layout):
+    """pa_anneal from an ordered population (one energy bin) at high
+    temperature, where the energy window widens by two orders of magnitude
+    within the first steps.  Every step matches the oracle."""
+    print("case anneal wide window layout=%s" % layout, flush=True)
+    L, R, theta = 64, 400, 5
+    g = pa.Run(L, R, seed=3, layout=layout)
+    o = oracle.Run(L, R, seed=3)
+    s = np.ones((R, L, L), np.int8)
+    g.upload_population(s, step=1, beta=0.05)
+    o.set_population(s, step=1, beta=0.05)
+    trace = []
+    for b in _fixed_betas(1, 0.05, 0.3, 0.05):
+        o.resample(b)
+        o.sweep(theta)
+        trace.append(o.measure())
+    obs = g.anneal(beta_f=0.3, dbeta=0.05, theta=theta)
+    assert len(obs) == len(trace) == 5
+    for go, oo in zip(obs, trace):
+        _same_obs(go, oo)
+    _same_population(g, o)
+
+
 @pytest.mark.parametrize("layout", LAYOUTS)
 def test_anneal_capacity_refusal_keeps_state(layout):
     """A step refused for capacity inside pa_anneal leaves the run at the last
