@@ -17,9 +17,10 @@ namespace {
 using namespace pa::dev;
 
 // ---------------------------------------------------------------------------
-// Population statistics (histogram, energy range, exact moment sums).  Every
-// block adds its replicas to the histogram and writes its partial sums; the
-// block that finishes last (counted in st->done) sums the partials into *st.
+// Population statistics (histogram, energy range, exact moment sums).  Each
+// chunk of kBlock replicas is added to the histogram and gets its partial sums,
+// by the workgroups in turn; the workgroup that finishes last (counted in
+// st->done) sums the partials into *st.
 // With `host` (pinned host memory, device view) that block also writes the
 // statistics block and the occupied window [emin, emax] of the histogram there
 // (bin b at byte 64 + 4 b), so the host reads them after the kernel without a
