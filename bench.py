@@ -454,6 +454,37 @@ def workload_resample_l256(pa, torch):
     return out
 
 
+def workload_sweeps(pa, torch):
+    """pa_sweep alone at each lattice size, bit store, beta = 0.44 (near the
+    critical point), after one resampling from the initial population: three
+    timed launches per shape (HIP events on the run's stream), the shortest
+    reported.  Shapes: L=16 R=100000, L=32 R=50000, L=64 R=20000 (theta=100;
+    register path) and L=128 R=50000 (theta=20), L=256 R=20000 (theta=5) (LDS
+    path)."""
+    out = {"workload": "pa_sweep alone, bit store, beta=0.44, one launch of theta sweeps per shape"}
+    s = torch.cuda.current_stream()
+    for L_, R_, theta in ((16, 100000, 100), (32, 50000, 100), (64, 20000, 100), (128, 50000, 20),
+                          (256, 20000, 5)):
+        run = pa.Run(L_, R_, seed=7, layout="bits")
+        run.resample(0.44)
+        run.sweep(theta)
+        ev = []
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            run.sweep(theta)
+            e1.record(s)
+            ev.append((e0, e1))
+        torch.cuda.synchronize()
+        ms = min(a.elapsed_time(b) for a, b in ev)
+        n = run.state()["R"]
+        out["L=%d" % L_] = {"R": n, "theta": theta, "ms_per_launch": ms,
+                            "flips_per_ns": L_ * L_ * theta * n / (ms * 1e6)}
+        print("sweeps L=%d R=%d %.3f ms" % (L_, n, ms), file=sys.stderr, flush=True)
+        run.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -468,7 +499,7 @@ def main():
                          "(known bytes) calibrates the HBM counters of a profiling run")
     ap.add_argument("--workload", default="l64",
                     choices=["l64", "l128_adaptive", "batch64", "l256_learned", "resample_l256", "l64_heatbath",
-                             "paper_tables"],
+                             "paper_tables", "sweeps"],
                     help="l64 (default) is the headline workload; the others print their own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -486,7 +517,8 @@ def main():
     if args.workload != "l64":
         fn = {"l128_adaptive": workload_l128_adaptive, "batch64": workload_batch64,
               "l256_learned": workload_l256_learned, "resample_l256": workload_resample_l256,
-              "l64_heatbath": workload_l64_heatbath, "paper_tables": workload_paper_tables}[args.workload]
+              "l64_heatbath": workload_l64_heatbath, "paper_tables": workload_paper_tables,
+              "sweeps": workload_sweeps}[args.workload]
         res = fn(pa, torch)
         res.pop("_model", None)
         print(json.dumps(res), flush=True)
