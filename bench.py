@@ -153,14 +153,23 @@ def time_step_calls(pa, torch, layout, steps):
             "sweep_ms_avg": sum(sweep_ms) / len(sweep_ms)}
 
 
-def cpu_baseline(seconds_target=15.0):
-    """The oracle, single-threaded, on a bounded sample of the same workload:
-    L = 64, theta = 100, fixed dbeta = 0.005, with R = 400 replicas for the
-    first temperature steps until about seconds_target of CPU time."""
+def host_cores():
+    """Cores this process may run on, at most 16 (the host CPU share of one
+    GPU on the measurement machines)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def _oracle_leg(Rs, threads, seconds_target):
+    """The oracle on L = 64, theta = 100, fixed dbeta = 0.005 with Rs
+    replicas, for the first temperature steps until about seconds_target."""
     import oracle
 
-    Rs = 400
     o = oracle.Run(L, Rs, seed=1)
+    o.set_threads(threads)
     o.init()
     o.measure()
     flips = 0
@@ -177,11 +186,22 @@ def cpu_baseline(seconds_target=15.0):
     return {
         "value": flips / (t * 1e9),
         "unit": "attempted spin flips/ns",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": "L=64, theta=100, dbeta=0.005, R=%d replicas, first %d temperature steps (%.2e flips, %.1f s); "
-                  "host CPU: %s" % (Rs, i, flips, t, platform.processor() or platform.machine()),
+        "sample": "L=64, theta=100, dbeta=0.005, R=%d replicas, first %d temperature steps (%.2e flips, %.1f s), "
+                  "%d thread(s) over replicas; host CPU: %s"
+                  % (Rs, i, flips, t, threads, platform.processor() or platform.machine()),
     }
+
+
+def cpu_baseline(seconds_target=10.0):
+    """The oracle on the host's cores (OpenMP over replicas, at most 16
+    threads), and on one core beside it, each on a bounded sample of the
+    same workload."""
+    n = host_cores()
+    out = _oracle_leg(400 * n, n, seconds_target) if n > 1 else _oracle_leg(400, 1, seconds_target)
+    out["single_core"] = _oracle_leg(400, 1, seconds_target) if n > 1 else dict(out)
+    return out
 
 
 def _exact_betaF(L, beta):
@@ -535,6 +555,11 @@ def main():
     head = res[layouts[0]]
     achieved = head["sweep_flips_avg"] * SLOTS_PER_FLIP / (head["sweep_ms_avg"] * 1e-3)
     traffic = measured_traffic()
+    # algorithmic HBM bytes of one sweep launch: every replica's spins read and
+    # written once for all theta sweeps (N/8 or N bytes each way) plus E and M
+    rep_bytes = L * L // 8 if layouts[0] == "bits" else L * L
+    n_rep = head["sweep_flips_avg"] / (L * L * THETA)
+    alg_bytes = 2 * n_rep * rep_bytes + 8 * n_rep
     out = {
         "metric": "attempted spin flips/ns + PA run wall-time (L=64,R=20000) on 1 MI355X vs HBM roofline",
         "value": round(head["flips_per_ns"], 3),
@@ -565,6 +590,8 @@ def main():
             "frac": round(achieved / VALU_PEAK_SLOTS, 4),
             "traffic": traffic,
             "hbm_frac": (round(traffic / (head["sweep_ms_avg"] * 1e-3) / HBM_PEAK, 5) if traffic else None),
+            "hbm_bytes_algorithmic": round(alg_bytes),
+            "hbm_frac_algorithmic": round(alg_bytes / (head["sweep_ms_avg"] * 1e-3) / HBM_PEAK, 5),
             "kernel_ms_avg": round(head["sweep_ms_avg"], 4),
             "flips_per_launch": head["sweep_flips_avg"],
             "kernel_share_of_run": round(head["sweep_share"], 4),

@@ -25,11 +25,13 @@
  *     synchronise that stream before returning.
  *   - Spin convention: +1 / -1; J = 1, h = 0; E = -sum over the 2N bonds;
  *     M = sum of spins.  Energies are multiples of 4 in [-2N, 2N].
- *   - Random numbers: Philox4x32-10 keyed by (seed_lo32, seed_hi32 ^ run_id),
- *     with counters derived from (replica slot, sweep number, colour, site) for
- *     the sweep, (parent slot, step) for resampling and (replica, site) for the
- *     initial state.  Results are therefore bit-reproducible for a given seed
- *     and schedule, independent of launch shapes.
+ *   - Random numbers: Philox4x32-10 keyed by the 64-bit seed, with counters
+ *     derived from (replica slot, sweep number, colour, site) for the sweep,
+ *     (parent slot, step) for resampling and (replica, site) for the initial
+ *     state; the last counter word holds 16 * run_id + the stream number, so
+ *     distinct (seed, run_id) pairs never share a stream.  Results are
+ *     therefore bit-reproducible for a given seed, run_id and schedule,
+ *     independent of launch shapes.
  */
 #ifndef PA_H
 #define PA_H
@@ -57,8 +59,10 @@ typedef enum {
 } pa_layout;
 
 enum {
-    PA_FLAG_MHR = 1,     /* accumulate the per-energy histograms used by pa_reweight */
-    PA_FLAG_HEATBATH = 2 /* sweeps use the heat-bath update instead of Metropolis (see pa_sweep) */
+    PA_FLAG_MHR = 1,      /* accumulate the per-energy histograms used by pa_reweight */
+    PA_FLAG_HEATBATH = 2, /* sweeps use the heat-bath update instead of Metropolis (see pa_sweep) */
+    PA_FLAG_LCG = 4       /* Metropolis sweeps take their uniforms from the in-line LCG variant
+                             (see pa_sweep); not with PA_FLAG_HEATBATH */
 };
 
 typedef struct {
@@ -67,7 +71,7 @@ typedef struct {
     int32_t capacity;   /* maximum population; 0 selects R + ceil(10 sqrt(R)) + 64 */
     int32_t layout;     /* pa_layout of the spin store */
     uint64_t seed;      /* Philox key material */
-    uint32_t run_id;    /* xored into the key's high word: independent runs */
+    uint32_t run_id;    /* < 2^28: independent runs of one seed (part of every random counter) */
     uint32_t flags;     /* PA_FLAG_* */
 } pa_params;
 
@@ -105,8 +109,8 @@ size_t pa_workspace_bytes(const pa_params* p);
  * configurations; ln Z_0 = N ln 2.  `d_workspace` is a device pointer to at
  * least `bytes` bytes, 256-byte aligned; `hip_stream` is a hipStream_t (NULL:
  * the null stream).  On success *out receives the handle.
- * Errors: PA_EINVAL (L not supported, R < 1, capacity < R, bad layout, NULL
- * pointers), PA_ENOMEM (bytes too small), PA_EHIP. */
+ * Errors: PA_EINVAL (L not supported, R < 1, capacity < R, bad layout,
+ * run_id >= 2^28, NULL pointers), PA_ENOMEM (bytes too small), PA_EHIP. */
 pa_status pa_init(const pa_params* p, void* d_workspace, size_t bytes, void* hip_stream, pa_run** out);
 
 /* nsweeps checkerboard Metropolis sweeps of every replica at the current beta
@@ -117,8 +121,12 @@ pa_status pa_init(const pa_params* p, void* d_workspace, size_t bytes, void* hip
  * instead (Sec. 2.1 names it as an alternative): the spin flips with
  * probability 1 / (1 + exp(2 beta k)), i.e. iff its 32-bit uniform is below
  * U_k = ceil(2^32 / (1 + exp(2 beta k))) for k = 2, 4, U_0 = 2^31,
- * U_{-k} = 2^32 - U_k.  Both use the same random streams.  Updates E_j and
- * M_j.  Asynchronous.
+ * U_{-k} = 2^32 - U_k.  Both use the same random streams.  With PA_FLAG_LCG
+ * the Metropolis uniforms come instead from the in-line generator of the
+ * paper's multi-spin-coded variant (Sec. 4): per sweep and per 32-site word of
+ * one colour, one Philox draw seeds r' = 1664525 r + 1013904223 mod 2^32, and
+ * the word's site b takes the (b+1)-th output; a different Markov chain with
+ * the same stationary distribution.  Updates E_j and M_j.  Asynchronous.
  * Errors: PA_EINVAL (nsweeps < 0), PA_ESTATE, PA_EHIP. */
 pa_status pa_sweep(pa_run* r, int32_t nsweeps);
 
@@ -211,6 +219,16 @@ pa_status pa_upload_population(pa_run* r, int32_t R_cur, const int8_t* spins, in
  * number of parents; counts must hold capacity entries. */
 pa_status pa_download_counts(pa_run* r, uint32_t* counts, int32_t* n);
 
+/* Test hook for the sweeps of L >= 128, which keep each replica in LDS and
+ * queue the sites whose uniform still ties with the threshold after its 8
+ * high bits, to be decided one per lane (Sec. 3, spin updates).  When more
+ * sites are tied than the queue holds (256 entries), every lane decides its own
+ * tied sites instead.  cap >= 0 lowers the number of entries a wave may use
+ * before taking that second route (0: always), so that tests reach it; values
+ * of 256 and above restore the default.  Results do not depend on cap.
+ * Errors: PA_EINVAL (cap < 0), PA_ESTATE. */
+pa_status pa_set_tie_queue_cap(pa_run* r, int32_t cap);
+
 /* ---- Batched runs: many independent PA runs advanced together. ----------
  * Every run has its own parameters (L, R, seed, run_id, layout, flags) and
  * schedule.  One pa_batch_step advances every unfinished run by one
@@ -272,10 +290,30 @@ size_t pa_batch_workspace_bytes(const pa_params* runs, int32_t nruns);
 
 /* Start nruns runs at beta_0 = 0 (Sec. 2.1 step 1) and measure them once.
  * `hip_stream` may be NULL: the batch then creates its own stream (graph
- * capture needs a non-null stream).  Errors: PA_EINVAL (invalid run
- * parameters or schedule, nruns < 1), PA_ENOMEM, PA_EHIP. */
+ * capture needs a non-null stream).  The sweep's work-group shape (waves per
+ * block, one per lattice size, store and update) is chosen by timing the
+ * candidates 1, 2, 4 and 8 on the batch's spare buffers.  Errors: PA_EINVAL
+ * (invalid run parameters or schedule, nruns < 1), PA_ENOMEM, PA_EHIP. */
 pa_status pa_batch_init(const pa_params* runs, const pa_schedule* sched, int32_t nruns, void* d_workspace,
                         size_t bytes, void* hip_stream, pa_batch** out);
+
+typedef struct {
+    int32_t waves_per_block;  /* 0: timed choice as in pa_batch_init; 1, 2, 4 or 8: that shape for every
+                                 group (a group whose LDS does not fit it takes the largest smaller
+                                 shape that fits); results do not depend on the shape */
+} pa_batch_options;
+
+/* pa_batch_init with options (opt may be NULL: the defaults).  Errors as
+ * pa_batch_init; PA_EINVAL also for a waves_per_block outside {0, 1, 2, 4, 8}. */
+pa_status pa_batch_init_ex(const pa_params* runs, const pa_schedule* sched, int32_t nruns,
+                           const pa_batch_options* opt, void* d_workspace, size_t bytes, void* hip_stream,
+                           pa_batch** out);
+
+/* Waves per block of the sweep launch that advances run `run`. */
+pa_status pa_batch_waves_per_block(const pa_batch* b, int32_t run, int32_t* wpb);
+
+/* pa_set_tie_queue_cap for every run of the batch, from the next step on. */
+pa_status pa_batch_set_tie_queue_cap(pa_batch* b, int32_t cap);
 
 /* One temperature step of every unfinished run.  *n_active (may be NULL)
  * receives the number of runs still below beta_f afterwards.  A run whose

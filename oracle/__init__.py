@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pa_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared"]
+CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
 
 
 def build(force=True):
@@ -72,6 +72,8 @@ def load(path):
         "orc_thresholds": (None, [dbl, P(u64), P(u64)]),
         "orc_hb_thresholds": (None, [dbl, P(u64), P(u64)]),
         "orc_set_heatbath": (None, [vp, i32]),
+        "orc_set_threads": (None, [vp, i32]),
+        "orc_set_lcg": (None, [vp, i32]),
         "orc_sweep": (None, [vp, i32]),
         "orc_resample": (i32, [vp, dbl, P(dbl), P(ctypes.c_int32)]),
         "orc_alpha": (dbl, [vp, dbl]),
@@ -89,6 +91,7 @@ def load(path):
         "orc_recount": (None, [vp, i32, P(ctypes.c_int32), P(ctypes.c_int32)]),
         "orc_tables": (dbl, [i32, i32, i32, vp, dbl, vp, vp]),
         "orc_set_slots": (None, [vp, vp]),
+        "orc_word_uniforms": (None, [vp, u64, i32, i32, i32, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -141,7 +144,7 @@ def default_capacity(R):
 class Run:
     """One PA run held by the oracle."""
 
-    def __init__(self, L, R, seed, run_id=0, capacity=0, lib_=None, heatbath=False):
+    def __init__(self, L, R, seed, run_id=0, capacity=0, lib_=None, heatbath=False, lcg=False):
         self.L, self.N, self.R = L, L * L, R
         self.capacity = capacity or default_capacity(R)
         self.lib = lib_ or lib()
@@ -150,11 +153,17 @@ class Run:
         if not self.h:
             raise ValueError("invalid oracle parameters")
         self.lib.orc_set_heatbath(self.h, 1 if self.heatbath else 0)
+        self.lcg = bool(lcg)
+        self.lib.orc_set_lcg(self.h, 1 if self.lcg else 0)
 
     def __del__(self):
         if getattr(self, "h", None):
             self.lib.orc_free(self.h)
             self.h = None
+
+    def set_threads(self, n):
+        """Share the replicas of init and sweeps out among n threads (timing)."""
+        self.lib.orc_set_threads(self.h, int(n))
 
     def init(self):
         self.lib.orc_init(self.h)
@@ -243,6 +252,12 @@ class Run:
             self._slots = np.ascontiguousarray(slots, dtype=np.int32)
             assert len(self._slots) == self.population
             self.lib.orc_set_slots(self.h, _ptr(self._slots))
+
+    def word_uniforms(self, g, c, j, v):
+        """The 32 site uniforms (uint32) of word v, colour c, slot j, sweep g."""
+        out = np.empty(32, np.uint32)
+        self.lib.orc_word_uniforms(self.h, int(g), int(c), int(j), int(v), _ptr(out))
+        return out
 
     def recount(self, j):
         e, m = ctypes.c_int32(), ctypes.c_int32()

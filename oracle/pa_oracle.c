@@ -10,7 +10,9 @@
  * "GPU accelerated population annealing algorithm", arXiv:1703.03676) step by
  * step, with every choice the paper leaves open fixed as stated below.  It is
  * written for clarity: int8 row-major spins, one site at a time, FP64 with no
- * contraction (build with -ffp-contract=off).
+ * contraction (build with -ffp-contract=off).  Only for timing, orc_init and
+ * orc_sweep may share the replicas out among threads (OpenMP); replicas are
+ * independent there, so results do not depend on it.
  *
  *   Sec. 2.1, enumerated algorithm ........ orc_init / orc_resample / orc_sweep
  *   Sec. 2.1, Eq. (Q) ...................... resample: Q_i via the energy histogram
@@ -28,16 +30,19 @@
  *       colour 0 then colour 1.  Within a colour the order is irrelevant because
  *       same-colour sites do not interact.
  *   R2  Within-colour index q = (y*L + x) >> 1 (a bijection onto [0, N/2)).
- *   R3  Random-number streams, all Philox4x32-10 with key (seed_lo, seed_hi^run):
- *         SWEEP-HIGH  counter (4v+k, 2g+c, j, 0), k=0..3, output w -> plane 4k+w
+ *   R3  Random-number streams, all Philox4x32-10 with key (seed_lo, seed_hi).
+ *       Counter word 3 carries the stream tag in its low 4 bits and the run
+ *       number above them, t(s) = 16 run + s (run < 2^28), so that every
+ *       (seed, run, stream) triple has streams of its own:
+ *         SWEEP-HIGH  counter (4v+k, 2g+c, j, t(0)), k=0..3, output w -> plane 4k+w
  *                     (v = q>>5 is the 32-site word of the site, g the run's
  *                     global sweep number, j the replica slot).  The high 16 bits
  *                     of the site's uniform are bit (q&31) of planes 0..15,
  *                     plane 0 most significant.
- *         SWEEP-LOW   counter (q>>3, 2g+c, j, 3), output (q>>1)&3, upper half for
- *                     even q, lower half for odd q: the low 16 bits.
- *         RESAMPLE    counter (j>>2, i, 0, 1), output j&3 (i = temperature step).
- *         INIT        counter (p>>7, 0, j, 2), output (p>>5)&3, bit p&31, with
+ *         SWEEP-LOW   counter (q>>3, 2g+c, j, t(3)), output (q>>1)&3, upper half
+ *                     for even q, lower half for odd q: the low 16 bits.
+ *         RESAMPLE    counter (j>>2, i, 0, t(1)), output j&3 (i = temperature step).
+ *         INIT        counter (p>>7, 0, j, t(2)), output (p>>5)&3, bit p&31, with
  *                     p = c*N/2 + q; a set bit means spin -1.
  *   R4  Metropolis: with k = s * (sum of the 4 neighbours), the energy change of a
  *       flip is 2k; k <= 0 always flips; k in {2,4} flips iff the site's 32-bit
@@ -60,6 +65,17 @@
  *       (the same streams as R3) satisfies x < U_k, with
  *       U_k = ceil(2^32 / (1 + e^{2 beta k})) for k = 2, 4, U_0 = 2^31 and
  *       U_{-k} = 2^32 - U_k, so that P(flip | k) + P(flip | -k) = 1 exactly.
+ *   R11 In-line LCG variant of the multi-spin-coded sweep (Sec. 4: one draw of
+ *       the base generator seeds, per word of spins and per update of it, a
+ *       linear congruential generator r' = A r + C mod 2^32 with A = 1664525,
+ *       C = 1013904223, which supplies the word's uniforms).  A word here is
+ *       the 32 same-colour sites q = 32v .. 32v+31 of one replica; its seed
+ *       for the update of colour c in sweep g is output c of Philox block
+ *       (v, g, j, t(4)) (stream LCG-SEED); site q = 32v + b takes the
+ *       (b+1)-th LCG output after the seed as its 32-bit uniform x, and
+ *       flips as in R4.  Every site consumes its output whether or not it
+ *       needs it, so positions are fixed.  Initial state and resampling keep
+ *       the Philox streams of R3, as the paper's variant does.
  */
 #include <math.h>
 #include <stdint.h>
@@ -121,6 +137,7 @@ typedef struct {
 typedef struct {
     int L, N, R, capacity;
     uint32_t key0, key1;
+    uint32_t tag;       /* 16 * run number: counter word 3 without the stream number */
     int Rcur;           /* R_i: current population size */
     int step;           /* i: number of resampling steps done */
     uint64_t sweeps;    /* g: number of sweeps done in this run */
@@ -136,6 +153,8 @@ typedef struct {
     int32_t *slot;      /* optional: random-stream slot of each replica in a sweep
                            (NULL: replica j uses slot j); for sampled checks */
     int heatbath;       /* 0: Metropolis sweeps (R4); 1: heat-bath sweeps (R10) */
+    int threads;        /* threads over replicas in orc_init / orc_sweep (1: serial) */
+    int lcg;            /* 1: site uniforms from the in-line LCG of R11 (Metropolis only) */
     /* multi-histogram accumulators, one bin per energy level */
     int64_t *H, *SA, *SM2;
     unsigned __int128 *SM4;
@@ -169,14 +188,16 @@ static void count_EM(const orc_run *r, const int8_t *s, int32_t *E, int32_t *M)
 
 orc_run *orc_new(int L, int R, int capacity, uint64_t seed, uint32_t run_id)
 {
-    if (L < 2 || (L & 1) || R < 1 || capacity < R) return NULL;
+    if (L < 2 || (L & 1) || R < 1 || capacity < R || run_id >= (1u << 28)) return NULL;
     orc_run *r = (orc_run *)calloc(1, sizeof(orc_run));
     r->L = L;
     r->N = L * L;
     r->R = R;
     r->capacity = capacity;
     r->key0 = (uint32_t)seed;
-    r->key1 = (uint32_t)(seed >> 32) ^ run_id;
+    r->key1 = (uint32_t)(seed >> 32);
+    r->tag = run_id << 4;
+    r->threads = 1;
     size_t ns = (size_t)capacity * r->N;
     r->spin = (int8_t *)calloc(ns, 1);
     r->spin2 = (int8_t *)calloc(ns, 1);
@@ -211,6 +232,7 @@ void orc_free(orc_run *r)
 void orc_init(orc_run *r)
 {
     int L = r->L, N = r->N, half = N / 2;
+#pragma omp parallel for schedule(static) num_threads(r->threads) if (r->threads > 1)
     for (int j = 0; j < r->R; ++j) {
         int8_t *s = spin_at(r, r->spin, j);
         for (int y = 0; y < L; ++y)
@@ -218,7 +240,7 @@ void orc_init(orc_run *r)
                 int c = (x + y) & 1;
                 int q = (y * L + x) >> 1;
                 uint32_t p = (uint32_t)(c * half + q);
-                uint32_t w = philox_word(r->key0, r->key1, p >> 7, 0, (uint32_t)j, 2, (int)((p >> 5) & 3));
+                uint32_t w = philox_word(r->key0, r->key1, p >> 7, 0, (uint32_t)j, r->tag | 2, (int)((p >> 5) & 3));
                 s[y * L + x] = ((w >> (p & 31)) & 1) ? -1 : 1;
             }
         count_EM(r, s, &r->E[j], &r->M[j]);
@@ -249,6 +271,32 @@ void orc_hb_thresholds(double beta, uint64_t *U2, uint64_t *U4)
     *U4 = (uint64_t)ceil(ldexp(1.0 / (1.0 + exp(8.0 * beta)), 32));
 }
 
+/* Threads over replicas in orc_init and orc_sweep (for timing only: the
+ * replicas of a half sweep are independent, so the result does not depend on
+ * it).  n < 1 means 1. */
+void orc_set_threads(orc_run *r, int n) { r->threads = n < 1 ? 1 : n; }
+
+/* Site uniforms of orc_sweep: 0 the Philox streams of R3, 1 the in-line LCG
+ * of R11 (for either update rule). */
+void orc_set_lcg(orc_run *r, int on) { r->lcg = on ? 1 : 0; }
+
+/* The LCG of R11: one step r -> A r + C mod 2^32. */
+#define LCG_A 1664525u
+#define LCG_C 1013904223u
+static uint32_t lcg_next(uint32_t x) { return LCG_A * x + LCG_C; }
+
+/* R11: the 32 uniforms of word v (colour c, replica slot j, sweep g): the
+ * word's seed from stream LCG-SEED, then one LCG output per site in bit
+ * order. */
+static void lcg_uniforms(const orc_run *r, uint64_t g, int c, int j, int v, uint32_t out[32])
+{
+    uint32_t x = philox_word(r->key0, r->key1, (uint32_t)v, (uint32_t)g, (uint32_t)j, r->tag | 4, c);
+    for (int b = 0; b < 32; ++b) {
+        x = lcg_next(x);
+        out[b] = x;
+    }
+}
+
 /* Select the update of orc_sweep: 0 Metropolis (R4), 1 heat-bath (R10). */
 void orc_set_heatbath(orc_run *r, int on) { r->heatbath = on ? 1 : 0; }
 
@@ -269,7 +317,7 @@ static void sweep_planes(const orc_run *r, uint64_t g, int c, int j, uint32_t v,
 {
     uint32_t ctr1 = (uint32_t)(2 * g + (uint64_t)c);
     for (uint32_t k = 0; k < 4; ++k) {
-        uint32_t ctr[4] = {4 * v + k, ctr1, (uint32_t)j, 0}, key[2] = {r->key0, r->key1}, out[4];
+        uint32_t ctr[4] = {4 * v + k, ctr1, (uint32_t)j, r->tag | 0}, key[2] = {r->key0, r->key1}, out[4];
         philox4x32_10(ctr, key, out);
         for (int w = 0; w < 4; ++w) planes[4 * k + w] = out[w];
     }
@@ -284,7 +332,7 @@ static uint32_t site_uniform(const orc_run *r, uint64_t g, int c, int j, int q, 
     uint32_t hi = 0;
     for (int p = 0; p < 16; ++p) hi = (hi << 1) | ((planes[p] >> bit) & 1u);
     uint32_t ctr1 = (uint32_t)(2 * g + (uint64_t)c);
-    uint32_t low_word = philox_word(r->key0, r->key1, (uint32_t)q >> 3, ctr1, (uint32_t)j, 3, (q >> 1) & 3);
+    uint32_t low_word = philox_word(r->key0, r->key1, (uint32_t)q >> 3, ctr1, (uint32_t)j, r->tag | 3, (q >> 1) & 3);
     uint32_t lo = (q & 1) ? (low_word & 0xFFFFu) : (low_word >> 16);
     return (hi << 16) | lo;
 }
@@ -301,13 +349,20 @@ void orc_sweep(orc_run *r, int nsweeps)
     orc_hb_thresholds(r->beta, &U2, &U4);
     for (int t = 0; t < nsweeps; ++t) {
         uint64_t g = r->sweeps;
-        for (int c = 0; c < 2; ++c)
+        for (int c = 0; c < 2; ++c) {
+            /* replicas are independent within a half sweep: with threads set,
+             * they are shared out among them; the result is the same */
+#pragma omp parallel for schedule(dynamic, 16) num_threads(r->threads) if (r->threads > 1)
             for (int j = 0; j < r->Rcur; ++j) {
                 int8_t *s = spin_at(r, r->spin, j);
                 int slot = r->slot ? r->slot[j] : j;
                 for (int v = 0; 32 * v < half; ++v) {
-                    uint32_t planes[16];
-                    sweep_planes(r, g, c, slot, (uint32_t)v, planes);
+                    uint32_t planes[16], lcg_u[32];
+                    if (r->lcg) {
+                        lcg_uniforms(r, g, c, slot, v, lcg_u);
+                    } else {
+                        sweep_planes(r, g, c, slot, (uint32_t)v, planes);
+                    }
                     for (int q = 32 * v; q < 32 * v + 32 && q < half; ++q) {
                         int y = q / hw;
                         int x = 2 * (q % hw) + ((y + c) & 1);
@@ -318,12 +373,14 @@ void orc_sweep(orc_run *r, int nsweeps)
                         int flip;
                         if (r->heatbath) {
                             uint64_t U = hb_threshold(k, U2, U4);
-                            flip = ((uint64_t)site_uniform(r, g, c, slot, q, planes) < U);
+                            uint32_t x = r->lcg ? lcg_u[q & 31] : site_uniform(r, g, c, slot, q, planes);
+                            flip = ((uint64_t)x < U);
                         } else if (k <= 0) {
                             flip = 1;
                         } else {
                             uint64_t T = (k == 2) ? T2 : T4;
-                            flip = ((uint64_t)site_uniform(r, g, c, slot, q, planes) < T);
+                            uint32_t x = r->lcg ? lcg_u[q & 31] : site_uniform(r, g, c, slot, q, planes);
+                            flip = ((uint64_t)x < T);
                         }
                         if (flip) {
                             s[y * L + x] = (int8_t)(-si);
@@ -333,6 +390,7 @@ void orc_sweep(orc_run *r, int nsweeps)
                     }
                 }
             }
+        }
         r->sweeps = g + 1;
     }
 }
@@ -396,7 +454,7 @@ int orc_resample(orc_run *r, double beta_next, double *lnQ_out, int32_t *Emin_ou
     int64_t total = 0;
     for (int j = 0; j < r->Rcur; ++j) {
         int b = bin_of(r, r->E[j]);
-        uint32_t x = philox_word(r->key0, r->key1, (uint32_t)j >> 2, (uint32_t)step, 0, 1, j & 3);
+        uint32_t x = philox_word(r->key0, r->key1, (uint32_t)j >> 2, (uint32_t)step, 0, r->tag | 1, j & 3);
         r->counts[j] = base[b] + (x <= thr[b] ? 1u : 0u);
         total += r->counts[j];
     }
@@ -635,6 +693,20 @@ void orc_set_slots(orc_run *r, const int32_t *slots)
     if (!slots) return;
     r->slot = (int32_t *)malloc(4 * (size_t)r->capacity);
     memcpy(r->slot, slots, 4 * (size_t)r->Rcur);
+}
+
+/* The 32-bit uniforms that decide the sites of word v (sites 32 v .. 32 v + 31
+ * of colour c) of replica slot j in sweep g (test hook for pins on the
+ * streams of reading R3: uniformity and independence between sites). */
+void orc_word_uniforms(const orc_run *r, uint64_t g, int c, int j, int v, uint32_t out[32])
+{
+    if (r->lcg) {
+        lcg_uniforms(r, g, c, j, v, out);
+        return;
+    }
+    uint32_t planes[16];
+    sweep_planes(r, g, c, j, (uint32_t)v, planes);
+    for (int b = 0; b < 32; ++b) out[b] = site_uniform(r, g, c, j, 32 * v + b, planes);
 }
 
 /* Full recount of E and M for replica j (invariant check of the incremental

@@ -20,6 +20,7 @@ PA_OK, PA_EINVAL, PA_ENOMEM, PA_ECAPACITY, PA_EHIP, PA_ESTATE, PA_EEXTINCT = 0, 
 PA_SPIN_INT8, PA_SPIN_BITS = 0, 1
 PA_FLAG_MHR = 1
 PA_FLAG_HEATBATH = 2
+PA_FLAG_LCG = 4
 LAYOUTS = {"int8": PA_SPIN_INT8, "bits": PA_SPIN_BITS}
 SUPPORTED_L = (16, 32, 64, 128, 256)
 
@@ -103,6 +104,11 @@ SIGNATURES = {
     "pa_upload_population": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, ctypes.c_int32, ctypes.c_uint64,
                                             ctypes.c_double, ctypes.c_double]),
     "pa_download_counts": (ctypes.c_int, [_vp, _vp, _P(ctypes.c_int32)]),
+    "pa_set_tie_queue_cap": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pa_batch_init_ex": (ctypes.c_int, [_P(Params), _P(Schedule), ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp,
+                                        _P(_vp)]),
+    "pa_batch_waves_per_block": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int32)]),
+    "pa_batch_set_tie_queue_cap": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "pa_batch_workspace_bytes": (ctypes.c_size_t, [_P(Params), ctypes.c_int32]),
     "pa_batch_init": (ctypes.c_int, [_P(Params), _P(Schedule), ctypes.c_int32, _vp, ctypes.c_size_t, _vp, _P(_vp)]),
     "pa_batch_step": (ctypes.c_int, [_vp, _P(ctypes.c_int32)]),
@@ -171,10 +177,10 @@ def _check(status, handle=None):
     raise PaError(status, msg)
 
 
-def make_params(L, R, seed, run_id=0, capacity=0, layout="bits", mhr=False, heatbath=False):
+def make_params(L, R, seed, run_id=0, capacity=0, layout="bits", mhr=False, heatbath=False, lcg=False):
     return Params(L=int(L), R=int(R), capacity=int(capacity), layout=LAYOUTS[layout] if isinstance(layout, str) else int(layout),
                   seed=int(seed), run_id=int(run_id),
-                  flags=(PA_FLAG_MHR if mhr else 0) | (PA_FLAG_HEATBATH if heatbath else 0))
+                  flags=(PA_FLAG_MHR if mhr else 0) | (PA_FLAG_HEATBATH if heatbath else 0) | (PA_FLAG_LCG if lcg else 0))
 
 
 def workspace_bytes(params):
@@ -213,11 +219,11 @@ class Run:
     """One PA run on the current GPU (C-ABI handle + torch-owned workspace)."""
 
     def __init__(self, L, R, seed, run_id=0, capacity=0, layout="bits", mhr=False, stream=None, device=None,
-                 heatbath=False):
+                 heatbath=False, lcg=False):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU available: libpa runs on the GPU only")
-        self.params = make_params(L, R, seed, run_id, capacity, layout, mhr, heatbath)
+        self.params = make_params(L, R, seed, run_id, capacity, layout, mhr, heatbath, lcg)
         nbytes = workspace_bytes(self.params)
         if nbytes == 0:
             raise PaError(PA_EINVAL, "invalid parameters")
@@ -330,6 +336,11 @@ class Run:
         _check(lib().pa_download_counts(self.h, _ptr(buf), ctypes.byref(n)), self.h)
         return buf[: n.value].copy()
 
+    def set_tie_queue_cap(self, cap):
+        """Limit the LDS-path tie queue to cap entries (0: every lane decides
+        its own ties); 256 or more restores the default."""
+        _check(lib().pa_set_tie_queue_cap(self.h, int(cap)), self.h)
+
 
 def make_schedule(beta_f=1.0, dbeta=0.0, alpha_star=0.0, alpha_tol=0.0, theta=1, mode="fixed", leader=0):
     return Schedule(beta_f=float(beta_f), dbeta=float(dbeta), alpha_star=float(alpha_star),
@@ -337,14 +348,18 @@ def make_schedule(beta_f=1.0, dbeta=0.0, alpha_star=0.0, alpha_tol=0.0, theta=1,
                     mode=STEP_MODES[mode] if isinstance(mode, str) else int(mode), leader=int(leader))
 
 
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("waves_per_block", ctypes.c_int32)]
+
+
 class Batch:
     """Many independent PA runs advanced together (one graph replay per step).
 
     runs: list of dicts with keys L, R, seed and optional run_id, capacity,
-    layout, mhr, heatbath.  schedules: list of dicts for make_schedule (or one dict for
-    all runs)."""
+    layout, mhr, heatbath, lcg.  schedules: list of dicts for make_schedule (or one dict for
+    all runs).  waves_per_block: 0 (timed choice) or a forced sweep shape."""
 
-    def __init__(self, runs, schedules, stream=None, device=None):
+    def __init__(self, runs, schedules, stream=None, device=None, waves_per_block=0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU available: libpa runs on the GPU only")
@@ -354,7 +369,7 @@ class Batch:
         self.specs = [dict(r) for r in runs]
         self.params = (Params * n)(*[make_params(r["L"], r["R"], r["seed"], r.get("run_id", 0), r.get("capacity", 0),
                                                  r.get("layout", "bits"), r.get("mhr", False),
-                                                 r.get("heatbath", False)) for r in runs])
+                                                 r.get("heatbath", False), r.get("lcg", False)) for r in runs])
         self.sched = (Schedule * n)(*[make_schedule(**sc) for sc in schedules])
         nbytes = lib().pa_batch_workspace_bytes(self.params, n)
         if nbytes == 0:
@@ -364,8 +379,9 @@ class Batch:
         self.stream = stream
         h = ctypes.c_void_p()
         sp = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
-        _check(lib().pa_batch_init(self.params, self.sched, n, ctypes.c_void_p(self.workspace.data_ptr()), nbytes,
-                                   sp, ctypes.byref(h)))
+        self.options = BatchOptions(waves_per_block=int(waves_per_block))
+        _check(lib().pa_batch_init_ex(self.params, self.sched, n, ctypes.byref(self.options),
+                                      ctypes.c_void_p(self.workspace.data_ptr()), nbytes, sp, ctypes.byref(h)))
         self.h = h
         self.n = n
 
@@ -426,6 +442,14 @@ class Batch:
         pr = ctypes.c_float()
         _check(lib().pa_batch_features(self.h, int(run), _ptr(x), ctypes.byref(v), ctypes.byref(pr)))
         return x, bool(v.value), pr.value
+
+    def waves_per_block(self, run):
+        w = ctypes.c_int32()
+        _check(lib().pa_batch_waves_per_block(self.h, int(run), ctypes.byref(w)))
+        return w.value
+
+    def set_tie_queue_cap(self, cap):
+        _check(lib().pa_batch_set_tie_queue_cap(self.h, int(cap)))
 
     def learned_stats(self, run):
         p, a = ctypes.c_int32(), ctypes.c_int32()

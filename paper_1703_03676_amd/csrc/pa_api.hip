@@ -48,7 +48,9 @@ bool make_layout(const pa_params* p, Layout* lo)
 {
     if (!p || !lattice_supported(p->L) || p->R < 1) return false;
     if (p->layout != PA_SPIN_INT8 && p->layout != PA_SPIN_BITS) return false;
-    if (p->flags & ~(uint32_t)(PA_FLAG_MHR | PA_FLAG_HEATBATH)) return false;
+    if (p->flags & ~(uint32_t)(PA_FLAG_MHR | PA_FLAG_HEATBATH | PA_FLAG_LCG)) return false;
+    if ((p->flags & PA_FLAG_HEATBATH) && (p->flags & PA_FLAG_LCG)) return false;
+    if (p->run_id >= (1u << 28)) return false;
     const int64_t cap = p->capacity ? p->capacity : default_capacity(p->R);
     if (cap < p->R || cap > (int64_t)1 << 30) return false;
     const int64_t N = (int64_t)p->L * p->L;
@@ -77,6 +79,15 @@ bool make_layout(const pa_params* p, Layout* lo)
     lo->total = o;
     return true;
 }
+
+// Per-call device scratch of the resampling path: copy counts and parent
+// indices (one per replica of the capacity), block totals, the copy-count
+// tables of the occupied energy window and the statistics partials, kept in
+// the run's workspace.
+struct Scratch {
+    uint32_t *counts, *parent, *bsum, *tbl;
+    pa::StatsPart* parts;
+};
 
 }  // namespace
 
@@ -115,9 +126,17 @@ struct pa_run {
     std::vector<int64_t> m_R;
     std::vector<double> w;  // host scratch: weights per energy bin
     host::WeightTable wpre; // weights of the next fixed step, filled while the GPU sweeps
+    uint32_t qcap = 0xFFFFFFFFu;  // tie-queue limit of the LDS-path sweeps (test hook)
 };
 
 namespace {
+
+int update_of(const pa_params& p)
+{
+    if (p.flags & PA_FLAG_HEATBATH) return pa::kHeatbath;
+    if (p.flags & PA_FLAG_LCG) return pa::kLcg;
+    return pa::kMetropolis;
+}
 
 pa_status fail_hip(pa_run* r, hipError_t e, const char* what)
 {
@@ -138,10 +157,13 @@ pa_status usable(const pa_run* r)
     return r->broken ? PA_ESTATE : PA_OK;
 }
 
-void key_of(const pa_run* r, uint32_t* k0, uint32_t* k1)
+// Philox key (the seed) and the run's part of counter word 3 (16 * run_id),
+// so that distinct (seed, run_id) pairs never share a random stream.
+void key_of(const pa_run* r, uint32_t* k0, uint32_t* k1, uint32_t* tag)
 {
     *k0 = (uint32_t)r->p.seed;
-    *k1 = (uint32_t)(r->p.seed >> 32) ^ r->p.run_id;
+    *k1 = (uint32_t)(r->p.seed >> 32);
+    *tag = r->p.run_id << 4;
 }
 
 pa_status launch_sweeps(pa_run* r, int32_t nsweeps, bool init)
@@ -154,11 +176,12 @@ pa_status launch_sweeps(pa_run* r, int32_t nsweeps, bool init)
     a.n_rep = (int32_t)r->R_cur;
     a.nsweeps = nsweeps;
     a.g0 = (uint32_t)r->sweeps;
-    key_of(r, &a.key0, &a.key1);
+    key_of(r, &a.key0, &a.key1, &a.tag);
     const bool hb = (r->p.flags & PA_FLAG_HEATBATH) != 0;
     host::sweep_thresholds(hb, r->beta, &a.t2h, &a.t2l, &a.t4h, &a.t4l);
     a.init = init ? 1 : 0;
-    HIPCHK(pa::launch_sweep(r->L, r->p.layout, hb, a, r->stream));
+    a.qcap = r->qcap;
+    HIPCHK(pa::launch_sweep(r->L, r->p.layout, update_of(r->p), a, r->stream));
     return PA_OK;
 }
 
@@ -181,12 +204,14 @@ pa_status read_host_stats(pa_run* r, DevStats* out)
 // Brings the histogram and the integer sums of the current population to the
 // host.  With `record` the measurement is also added to the multi-histogram
 // accumulators (only then is a cached result not reused).
-pa_status refresh_stats(pa_run* r, bool record)
+Scratch run_scratch(const pa_run* r) { return Scratch{r->counts, r->parent, r->bsum, r->tbl, r->parts}; }
+
+pa_status refresh_stats(pa_run* r, bool record, pa::StatsPart* parts)
 {
     if (!record && r->stats_version == r->version) return PA_OK;
     HIPCHK(pa::launch_stats_reset(r->stats, r->hist, r->nbins, r->stream));
     HIPCHK(pa::launch_stats(r->E[r->cur], r->M[r->cur], (int32_t)r->R_cur, nullptr, r->N, r->stats, r->hist,
-                            r->nbins, record ? 1 : 0, r->mhr, r->parts, r->hstats_dev, r->stream));
+                            r->nbins, record ? 1 : 0, r->mhr, parts, r->hstats_dev, r->stream));
     HIPCHK(hipStreamSynchronize(r->stream));
     const pa_status st = read_host_stats(r, &r->h_stats);
     if (st != PA_OK) return st;
@@ -206,24 +231,24 @@ host::Hist window(const pa_run* r) { return host::hist_window(r->h_hist.data(), 
 // Without `copy` the caller's next sweep gathers the parents itself.  The
 // scatter also clears the statistics block and the histogram, so the
 // statistics of the resampled population need no separate reset.
-pa_status queue_resample(pa_run* r, double beta_next, bool copy, double* lnQ, int32_t* Emin)
+pa_status queue_resample(pa_run* r, double beta_next, bool copy, double* lnQ, int32_t* Emin, const Scratch& sc)
 {
     const host::Hist h = window(r);
     const int bmin = h.bmin, nwin = h.bmax - h.bmin + 1;
     *Emin = h.energy(bmin);
     uint32_t* tab = (uint32_t*)r->pinned;
     *lnQ = host::resample_tables(h, r->p.R, r->R_cur, beta_next - r->beta, tab, r->w, &r->wpre);
-    HIPCHK(hipMemcpyAsync(r->tbl, tab, (size_t)nwin * 8, hipMemcpyHostToDevice, r->stream));
-    uint32_t k0, k1;
-    key_of(r, &k0, &k1);
+    HIPCHK(hipMemcpyAsync(sc.tbl, tab, (size_t)nwin * 8, hipMemcpyHostToDevice, r->stream));
+    uint32_t k0, k1, tag;
+    key_of(r, &k0, &k1, &tag);
     const int32_t n = (int32_t)r->R_cur;
     const int nxt = r->cur ^ 1;
-    HIPCHK(pa::launch_counts(r->E[r->cur], n, r->N, bmin, nwin, r->tbl, (uint32_t)(r->step + 1), k0, k1, r->counts,
-                             r->bsum, r->stream));
-    HIPCHK(pa::launch_scatter(r->counts, r->bsum, n, r->lo.capacity, r->parent, r->stats, r->hist, r->nbins,
+    HIPCHK(pa::launch_counts(r->E[r->cur], n, r->N, bmin, nwin, sc.tbl, (uint32_t)(r->step + 1), k0, k1, tag,
+                             sc.counts, sc.bsum, r->stream));
+    HIPCHK(pa::launch_scatter(sc.counts, sc.bsum, n, r->lo.capacity, sc.parent, r->stats, r->hist, r->nbins,
                               r->stream));
     if (copy)
-        HIPCHK(pa::launch_copy(r->spin[r->cur], r->E[r->cur], r->M[r->cur], r->parent, &r->stats->r_new,
+        HIPCHK(pa::launch_copy(r->spin[r->cur], r->E[r->cur], r->M[r->cur], sc.parent, &r->stats->r_new,
                                r->lo.capacity, r->lo.rep_bytes, r->spin[nxt], r->E[nxt], r->M[nxt], r->stream));
     r->counts_n = n;
     return PA_OK;
@@ -359,17 +384,19 @@ pa_status pa_sweep(pa_run* r, int32_t nsweeps)
     return PA_OK;
 }
 
-pa_status pa_resample(pa_run* r, double beta_next, pa_resample_info* out)
+// pa_resample: the statistics, the copy counts, their prefix sum, the parent
+// indices and the replica copy, with the per-call device scratch `sc`.
+static pa_status resample_with(pa_run* r, double beta_next, pa_resample_info* out, const Scratch& sc)
 {
     pa_status st = usable(r);
     if (st != PA_OK) return st;
     if (!std::isfinite(beta_next) || beta_next < r->beta) return PA_EINVAL;
-    st = refresh_stats(r, false);
+    st = refresh_stats(r, false, sc.parts);
     if (st != PA_OK) return st;
 
     double lnQ;
     int32_t Emin;
-    st = queue_resample(r, beta_next, true, &lnQ, &Emin);
+    st = queue_resample(r, beta_next, true, &lnQ, &Emin, sc);
     if (st != PA_OK) return st;
     // the host waits only for the total; the copy runs on meanwhile
     uint32_t* rn = (uint32_t*)(r->pinned + r->pinned_bytes - 8);
@@ -389,6 +416,13 @@ pa_status pa_resample(pa_run* r, double beta_next, pa_resample_info* out)
     return PA_OK;
 }
 
+pa_status pa_resample(pa_run* r, double beta_next, pa_resample_info* out)
+{
+    const pa_status st = usable(r);
+    if (st != PA_OK) return st;
+    return resample_with(r, beta_next, out, run_scratch(r));
+}
+
 pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs* out, float* sweep_ms, int32_t cap,
                     int32_t* nsteps)
 {
@@ -406,14 +440,14 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
         return PA_EINVAL;
     }
     const bool record = (r->p.flags & PA_FLAG_MHR) != 0;
-    st = refresh_stats(r, false);
+    st = refresh_stats(r, false, r->parts);
     if (st != PA_OK) return st;
     if (sweep_ms && cap > 0 && !r->ev_t0) {
         HIPCHK(hipEventCreate(&r->ev_t0));
         HIPCHK(hipEventCreate(&r->ev_t1));
     }
-    uint32_t k0, k1;
-    key_of(r, &k0, &k1);
+    uint32_t k0, k1, tag;
+    key_of(r, &k0, &k1, &tag);
     int32_t done = 0;
     // fixed schedule: inverse temperature of step i, not below the one before
     auto fixed_beta = [&](int64_t i, double prev) {
@@ -439,7 +473,7 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
         int32_t Emin;
         // with sweeps, the sweep kernel loads every child from its parent: the
         // replica copy and the sweep's load are one pass over the store
-        st = queue_resample(r, bn, sc->theta == 0, &lnQ, &Emin);
+        st = queue_resample(r, bn, sc->theta == 0, &lnQ, &Emin, run_scratch(r));
         if (st != PA_OK) return st;
         const int nxt = r->cur ^ 1;
         const uint32_t* n_dev = &r->stats->r_new;
@@ -457,11 +491,13 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
             a.g0 = (uint32_t)r->sweeps;
             a.key0 = k0;
             a.key1 = k1;
+            a.tag = tag;
+            a.qcap = r->qcap;
             const bool hb = (r->p.flags & PA_FLAG_HEATBATH) != 0;
             host::sweep_thresholds(hb, bn, &a.t2h, &a.t2l, &a.t4h, &a.t4l);
             const bool timed = sweep_ms && done < cap;
             if (timed) HIPCHK(hipEventRecord(r->ev_t0, r->stream));
-            HIPCHK(pa::launch_sweep(r->L, r->p.layout, hb, a, r->stream));
+            HIPCHK(pa::launch_sweep(r->L, r->p.layout, update_of(r->p), a, r->stream));
             if (timed) HIPCHK(hipEventRecord(r->ev_t1, r->stream));
         }
         // (the scatter of queue_resample has cleared the statistics)
@@ -513,7 +549,7 @@ pa_status pa_alpha(pa_run* r, double beta_prime, double* alpha)
     pa_status st = usable(r);
     if (st != PA_OK) return st;
     if (!alpha || !std::isfinite(beta_prime)) return PA_EINVAL;
-    st = refresh_stats(r, false);
+    st = refresh_stats(r, false, r->parts);
     if (st != PA_OK) return st;
     std::vector<double> w;
     *alpha = host::overlap(window(r), r->p.R, r->R_cur, beta_prime - r->beta, w);
@@ -526,7 +562,7 @@ pa_status pa_adapt_beta(pa_run* r, double alpha_star, double beta_f, double* bet
     if (st != PA_OK) return st;
     if (!beta_next || !(alpha_star > 0.0 && alpha_star < 1.0) || !std::isfinite(beta_f) || beta_f < r->beta)
         return PA_EINVAL;
-    st = refresh_stats(r, false);
+    st = refresh_stats(r, false, r->parts);
     if (st != PA_OK) return st;
     std::vector<double> w;
     if (!host::adapt_beta(window(r), r->p.R, r->R_cur, r->beta, beta_f, alpha_star, beta_next, alpha_at_next, w))
@@ -540,7 +576,7 @@ pa_status pa_observables(pa_run* r, pa_obs* o)
     if (st != PA_OK) return st;
     if (!o) return PA_EINVAL;
     const bool record = (r->p.flags & PA_FLAG_MHR) != 0;
-    st = refresh_stats(r, record);
+    st = refresh_stats(r, record, r->parts);
     if (st != PA_OK) return st;
     host::observables(r->h_stats, r->R_cur, r->N, r->beta, r->lnZ, r->lnQ_last, o);
     if (record) {
@@ -570,6 +606,15 @@ pa_status pa_weighted_average(int32_t N, int32_t nruns, int32_t nb, const pa_obs
 {
     if (N < 1 || nruns < 1 || nb < 0 || (nb > 0 && (!obs || !out))) return PA_EINVAL;
     return host::weighted_average(N, nruns, nb, obs, out) ? PA_OK : PA_EINVAL;
+}
+
+pa_status pa_set_tie_queue_cap(pa_run* r, int32_t cap)
+{
+    pa_status st = usable(r);
+    if (st != PA_OK) return st;
+    if (cap < 0) return PA_EINVAL;
+    r->qcap = (uint32_t)cap;
+    return PA_OK;
 }
 
 pa_status pa_state(const pa_run* r, pa_state_info* out)

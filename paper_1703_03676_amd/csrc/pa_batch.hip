@@ -58,7 +58,9 @@ struct RunDev {
     DevMhr mhr;
     int32_t L, N, nbins, capacity, layout, R;
     uint32_t rep_bytes;
-    uint32_t key0, key1;
+    uint32_t key0, key1;  // Philox key: the run's seed
+    uint32_t tag;         // 16 * run_id: counter word 3 without the stream number
+    uint32_t qcap;        // tie-queue limit of the LDS-path sweeps (SweepArgs::qcap)
 };
 
 struct StepDev {
@@ -137,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void b_counts(const Item* __restrict__ item
     uint32_t c = 0;
     if (j < st.n_parent) {
         const int b = ((rd.E[st.cur][j] + 2 * rd.N) >> 2) - st.bmin;
-        const uint32_t x = pick(philox10((uint32_t)j >> 2, st.step, 0u, kStreamResample, rd.key0, rd.key1),
+        const uint32_t x = pick(philox10((uint32_t)j >> 2, st.step, 0u, rd.tag | kStreamResample, rd.key0, rd.key1),
                                 (uint32_t)j & 3u);
         if (b >= 0 && b < st.nwin) {
             const uint32_t base = tbl[st.tbl_off + 2 * b], thr = tbl[st.tbl_off + 2 * b + 1];
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(kBlock) void b_copy(const Item* __restrict__ items,
 }
 
 // Item blk covers waves [blk * wpb, (blk + 1) * wpb) of the run (wpb = blockDim.x / 64).
-template <int L, bool INT8, bool HB>
+template <int L, bool INT8, int U>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_min_waves<L>(), 8))) void b_sweep(const Item* __restrict__ items, const RunDev* __restrict__ runs,
                                                const StepDev* __restrict__ steps, const ResultDev* __restrict__ res)
 {
@@ -251,13 +253,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_min_w
     a.g0 = st.g0;
     a.key0 = rd.key0;
     a.key1 = rd.key1;
+    a.tag = rd.tag;
+    a.qcap = rd.qcap;
     a.t2h = st.t2h;
     a.t2l = st.t2l;
     a.t4h = st.t4h;
     a.t4l = st.t4l;
     a.init = st.init;
     const int wpb = (int)(blockDim.x >> 6);
-    sweep_waves<L, INT8, HB>(a, it.blk * wpb, wpb, lds_dyn);
+    sweep_waves<L, INT8, U == pa::kHeatbath, U == pa::kLcg>(a, it.blk * wpb, wpb, lds_dyn);
 }
 
 __global__ __launch_bounds__(kBlock) void b_stats_reset(const RunDev* __restrict__ runs,
@@ -391,7 +395,9 @@ bool valid_params(const pa_params& p)
 {
     if (!lattice_supported(p.L) || p.R < 1) return false;
     if (p.layout != PA_SPIN_INT8 && p.layout != PA_SPIN_BITS) return false;
-    if (p.flags & ~(uint32_t)(PA_FLAG_MHR | PA_FLAG_HEATBATH)) return false;
+    if (p.flags & ~(uint32_t)(PA_FLAG_MHR | PA_FLAG_HEATBATH | PA_FLAG_LCG)) return false;
+    if ((p.flags & PA_FLAG_HEATBATH) && (p.flags & PA_FLAG_LCG)) return false;
+    if (p.run_id >= (1u << 28)) return false;
     const int64_t cap = p.capacity ? p.capacity : default_capacity(p.R);
     return cap >= p.R && cap <= ((int64_t)1 << 30);
 }
@@ -427,12 +433,19 @@ struct BatchLayout {
 
 struct Group {
     int L, layout;
-    bool hb;  // heat-bath runs (PA_FLAG_HEATBATH)
+    int upd;  // update rule of its runs (pa::Update)
     int wpb;
     size_t item_off, n_items;
 };
 
 bool heatbath(const pa_params& p) { return (p.flags & PA_FLAG_HEATBATH) != 0; }
+
+int update_of(const pa_params& p)
+{
+    if (p.flags & PA_FLAG_HEATBATH) return pa::kHeatbath;
+    if (p.flags & PA_FLAG_LCG) return pa::kLcg;
+    return pa::kMetropolis;
+}
 
 bool make_batch_layout(const pa_params* runs, int nruns, BatchLayout* bl)
 {
@@ -625,6 +638,7 @@ struct pa_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     pa::batch::Pool* pool = nullptr;
+    pa_batch_options opt{0};  // forced launch shape (0: autotuned)
     bool broken = false;
     std::string last_error;
 };
@@ -644,26 +658,35 @@ pa_status fail_hip(pa_batch* b, hipError_t e, const char* what)
         if (e_ != hipSuccess) return fail_hip(b, e_, #expr);  \
     } while (0)
 
-template <int L, bool INT8, bool HB>
+template <int L, bool INT8, int U>
 hipError_t launch_group_t(const Item* items, size_t n, int wpb, const RunDev* rd, const StepDev* st,
                           const ResultDev* rs, hipStream_t s)
 {
     using Gm = pa::dev::Geo<L>;
     const size_t lds = (size_t)Gm::lds_words(wpb) * 4;
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL((b_sweep<L, INT8, HB>), dim3((unsigned)n), dim3(64 * wpb), lds, s, items, rd, st, rs);
+    hipLaunchKernelGGL((b_sweep<L, INT8, U>), dim3((unsigned)n), dim3(64 * wpb), lds, s, items, rd, st, rs);
     return hipGetLastError();
 }
 
+template <int L, bool INT8>
+hipError_t launch_group_u(int upd, const Item* items, size_t n, int wpb, const RunDev* rd, const StepDev* st,
+                          const ResultDev* rs, hipStream_t s)
+{
+    switch (upd) {
+    case pa::kMetropolis: return launch_group_t<L, INT8, pa::kMetropolis>(items, n, wpb, rd, st, rs, s);
+    case pa::kHeatbath: return launch_group_t<L, INT8, pa::kHeatbath>(items, n, wpb, rd, st, rs, s);
+    case pa::kLcg: return launch_group_t<L, INT8, pa::kLcg>(items, n, wpb, rd, st, rs, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <int L>
-hipError_t launch_group_l(bool i8, bool hb, const Item* items, size_t n, int wpb, const RunDev* rd,
+hipError_t launch_group_l(bool i8, int upd, const Item* items, size_t n, int wpb, const RunDev* rd,
                           const StepDev* st, const ResultDev* rs, hipStream_t s)
 {
-    if (hb)
-        return i8 ? launch_group_t<L, true, true>(items, n, wpb, rd, st, rs, s)
-                  : launch_group_t<L, false, true>(items, n, wpb, rd, st, rs, s);
-    return i8 ? launch_group_t<L, true, false>(items, n, wpb, rd, st, rs, s)
-              : launch_group_t<L, false, false>(items, n, wpb, rd, st, rs, s);
+    return i8 ? launch_group_u<L, true>(upd, items, n, wpb, rd, st, rs, s)
+              : launch_group_u<L, false>(upd, items, n, wpb, rd, st, rs, s);
 }
 
 hipError_t launch_group(const Group& g, const Item* items, size_t n, int wpb, const RunDev* rd, const StepDev* st,
@@ -671,11 +694,11 @@ hipError_t launch_group(const Group& g, const Item* items, size_t n, int wpb, co
 {
     const bool i8 = g.layout == PA_SPIN_INT8;
     switch (g.L) {
-    case 16: return launch_group_l<16>(i8, g.hb, items, n, wpb, rd, st, rs, s);
-    case 32: return launch_group_l<32>(i8, g.hb, items, n, wpb, rd, st, rs, s);
-    case 64: return launch_group_l<64>(i8, g.hb, items, n, wpb, rd, st, rs, s);
-    case 128: return launch_group_l<128>(i8, g.hb, items, n, wpb, rd, st, rs, s);
-    case 256: return launch_group_l<256>(i8, g.hb, items, n, wpb, rd, st, rs, s);
+    case 16: return launch_group_l<16>(i8, g.upd, items, n, wpb, rd, st, rs, s);
+    case 32: return launch_group_l<32>(i8, g.upd, items, n, wpb, rd, st, rs, s);
+    case 64: return launch_group_l<64>(i8, g.upd, items, n, wpb, rd, st, rs, s);
+    case 128: return launch_group_l<128>(i8, g.upd, items, n, wpb, rd, st, rs, s);
+    case 256: return launch_group_l<256>(i8, g.upd, items, n, wpb, rd, st, rs, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -710,7 +733,7 @@ std::vector<Item> sweep_items(const pa_batch* b, const Group& g, int wpb)
     const int per_block = reps_per_wave(g.L) * wpb;
     for (int r = 0; r < b->nruns; ++r) {
         const pa_params& p = b->runs[(size_t)r].p;
-        if (p.L != g.L || p.layout != g.layout || heatbath(p) != g.hb) continue;
+        if (p.L != g.L || p.layout != g.layout || update_of(p) != g.upd) continue;
         const int cap = b->lo.runs[(size_t)r].capacity;
         const int nb = (cap + per_block - 1) / per_block;
         for (int k = 0; k < nb; ++k) it.push_back(Item{r, k});
@@ -849,16 +872,28 @@ size_t pa_batch_workspace_bytes(const pa_params* runs, int32_t nruns)
     return make_batch_layout(runs, nruns, &bl) ? bl.total : 0;
 }
 
-static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int32_t nruns, void* d_workspace,
-                            size_t bytes, void* hip_stream, pa_batch** out);
+static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int32_t nruns,
+                            const pa_batch_options* opt, void* d_workspace, size_t bytes, void* hip_stream,
+                            pa_batch** out);
 
 pa_status pa_batch_init(const pa_params* runs, const pa_schedule* sched, int32_t nruns, void* d_workspace,
                         size_t bytes, void* hip_stream, pa_batch** out)
 {
+    return pa_batch_init_ex(runs, sched, nruns, nullptr, d_workspace, bytes, hip_stream, out);
+}
+
+pa_status pa_batch_init_ex(const pa_params* runs, const pa_schedule* sched, int32_t nruns,
+                           const pa_batch_options* opt, void* d_workspace, size_t bytes, void* hip_stream,
+                           pa_batch** out)
+{
     if (!out) return PA_EINVAL;
     *out = nullptr;
+    if (opt) {
+        const int w = opt->waves_per_block;
+        if (!(w == 0 || w == 1 || w == 2 || w == 4 || w == 8)) return PA_EINVAL;
+    }
     pa_batch* b = nullptr;
-    const pa_status st = batch_init(runs, sched, nruns, d_workspace, bytes, hip_stream, &b);
+    const pa_status st = batch_init(runs, sched, nruns, opt, d_workspace, bytes, hip_stream, &b);
     if (st != PA_OK) {
         if (b && b->stream) (void)hipStreamSynchronize(b->stream);
         pa_batch_free(b);
@@ -868,8 +903,9 @@ pa_status pa_batch_init(const pa_params* runs, const pa_schedule* sched, int32_t
     return PA_OK;
 }
 
-static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int32_t nruns, void* d_workspace,
-                            size_t bytes, void* hip_stream, pa_batch** out)
+static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int32_t nruns,
+                            const pa_batch_options* opt, void* d_workspace, size_t bytes, void* hip_stream,
+                            pa_batch** out)
 {
     if (!runs || !sched || nruns < 1 || !d_workspace || ((uintptr_t)d_workspace) % kAlign) return PA_EINVAL;
     for (int r = 0; r < nruns; ++r) {
@@ -888,6 +924,7 @@ static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int
     b->nruns = nruns;
     b->lo = bl;
     b->ws = (uint8_t*)d_workspace;
+    if (opt) b->opt = *opt;
     *out = b;
     if (hip_stream) {
         b->stream = (hipStream_t)hip_stream;
@@ -938,7 +975,9 @@ static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int
         d.R = h.p.R;
         d.rep_bytes = (uint32_t)rl.rep_bytes;
         d.key0 = (uint32_t)h.p.seed;
-        d.key1 = (uint32_t)(h.p.seed >> 32) ^ h.p.run_id;
+        d.key1 = (uint32_t)(h.p.seed >> 32);
+        d.tag = h.p.run_id << 4;
+        d.qcap = 0xFFFFFFFFu;
     }
     if (hipHostMalloc((void**)&b->h_steps, bl.steps_bytes, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&b->h_download, bl.download_bytes, hipHostMallocDefault) != hipSuccess)
@@ -974,12 +1013,12 @@ static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int
     }
     b->n_copy_items = items.size() - b->copy_off;
     // sweep groups, one per (L, store, update)
-    std::map<std::tuple<int, int, bool>, int> seen;
+    std::map<std::tuple<int, int, int>, int> seen;
     for (int r = 0; r < nruns; ++r) {
-        const auto key = std::make_tuple(runs[r].L, runs[r].layout, heatbath(runs[r]));
+        const auto key = std::make_tuple(runs[r].L, runs[r].layout, update_of(runs[r]));
         if (!seen.count(key)) {
             seen[key] = (int)b->groups.size();
-            b->groups.push_back(Group{runs[r].L, runs[r].layout, heatbath(runs[r]), 1, 0, 0});
+            b->groups.push_back(Group{runs[r].L, runs[r].layout, update_of(runs[r]), 1, 0, 0});
         }
     }
     b->pool = new (std::nothrow) Pool((int)std::min<unsigned>(16u, std::max(1u, std::thread::hardware_concurrency())));
@@ -1256,6 +1295,29 @@ pa_status pa_batch_features(const pa_batch* b, int32_t run, float* x, int32_t* v
     return PA_OK;
 }
 
+pa_status pa_batch_set_tie_queue_cap(pa_batch* b, int32_t cap)
+{
+    if (!b || cap < 0) return PA_EINVAL;
+    if (b->broken) return PA_ESTATE;
+    for (RunDev& d : b->rundev) d.qcap = (uint32_t)cap;
+    BCHK(hipMemcpyAsync(b->d_rundev, b->rundev.data(), sizeof(RunDev) * b->rundev.size(), hipMemcpyHostToDevice,
+                        b->stream));
+    BCHK(hipStreamSynchronize(b->stream));
+    return PA_OK;
+}
+
+pa_status pa_batch_waves_per_block(const pa_batch* b, int32_t run, int32_t* wpb)
+{
+    if (!b || !wpb || run < 0 || run >= b->nruns) return PA_EINVAL;
+    const pa_params& p = b->runs[(size_t)run].p;
+    for (const Group& g : b->groups)
+        if (g.L == p.L && g.layout == p.layout && g.upd == update_of(p)) {
+            *wpb = g.wpb;
+            return PA_OK;
+        }
+    return PA_EINVAL;
+}
+
 pa_status pa_batch_learned_stats(const pa_batch* b, int32_t run, int32_t* proposals, int32_t* accepted)
 {
     if (!b || run < 0 || run >= b->nruns || !proposals || !accepted) return PA_EINVAL;
@@ -1291,14 +1353,14 @@ namespace {
 struct TuneKey {
     std::string arch;
     int L, layout;
-    bool hb;
+    int upd;
     int64_t reps;
     bool operator<(const TuneKey& o) const
     {
         if (arch != o.arch) return arch < o.arch;
         if (L != o.L) return L < o.L;
         if (layout != o.layout) return layout < o.layout;
-        if (hb != o.hb) return hb < o.hb;
+        if (upd != o.upd) return upd < o.upd;
         return reps < o.reps;
     }
 };
@@ -1319,14 +1381,21 @@ pa_status autotune(pa_batch* b)
     BCHK(hipEventCreate(&e1));
     std::vector<Item> it;
     for (Group& g : b->groups) {
+        if (b->opt.waves_per_block > 0) {
+            // a forced shape; where its LDS does not fit, the largest smaller one that does
+            int w = b->opt.waves_per_block;
+            while (w > 1 && sweep_lds_bytes(g.L, w) > 65536) w >>= 1;
+            g.wpb = w;
+            continue;
+        }
         int64_t reps = 0;
         for (int r = 0; r < b->nruns; ++r) {
             const RunHost& h = b->runs[(size_t)r];
-            if (h.p.L == g.L && h.p.layout == g.layout && heatbath(h.p) == g.hb) reps += h.p.R;
+            if (h.p.L == g.L && h.p.layout == g.layout && update_of(h.p) == g.upd) reps += h.p.R;
         }
         int64_t bucket = 1;
         while (bucket < reps) bucket <<= 1;
-        const TuneKey key{arch, g.L, g.layout, g.hb, bucket};
+        const TuneKey key{arch, g.L, g.layout, g.upd, bucket};
         {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             const auto f = g_tune_cache.find(key);
@@ -1339,14 +1408,14 @@ pa_status autotune(pa_batch* b)
             StepDev& d = sd[r];
             std::memset(&d, 0, sizeof(d));
             const RunHost& h = b->runs[(size_t)r];
-            if (h.p.L != g.L || h.p.layout != g.layout || heatbath(h.p) != g.hb) continue;
+            if (h.p.L != g.L || h.p.layout != g.layout || update_of(h.p) != g.upd) continue;
             d.active = 1;
             d.init = 1;
             d.cur = 1;  // spare buffer
             d.n_parent = h.p.R;
             d.nsweeps = 4;
             d.g0 = 0x40000000u;
-            host::sweep_thresholds(g.hb, 0.44, &d.t2h, &d.t2l, &d.t4h, &d.t4l);
+            host::sweep_thresholds(g.upd == pa::kHeatbath, 0.44, &d.t2h, &d.t2l, &d.t4h, &d.t4l);
         }
         BCHK(hipMemcpyAsync(b->d_steps, b->h_steps, b->lo.steps_bytes, hipMemcpyHostToDevice, b->stream));
         float best = 1e30f;

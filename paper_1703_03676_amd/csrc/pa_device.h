@@ -111,11 +111,14 @@ __device__ __forceinline__ uint32_t pick(const U4& v, uint32_t i)
     return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
 }
 
-// Random-stream tags (counter word 3).
+// Random-stream numbers: the low 4 bits of counter word 3, whose upper bits
+// hold the run number (SweepArgs::tag = 16 * run), so every (seed, run,
+// stream) has streams of its own.
 constexpr uint32_t kStreamSweepHigh = 0;
 constexpr uint32_t kStreamResample = 1;
 constexpr uint32_t kStreamInit = 2;
 constexpr uint32_t kStreamSweepLow = 3;
+constexpr uint32_t kStreamLcgSeed = 4;
 
 template <int L>
 struct Geo {
@@ -291,9 +294,9 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_
         // blocks 0, 1 and 2 are computed together (three independent chains),
         // since the first eight planes leave some site of the wave tied almost
         // surely (the wave holds about 2000 sites that need a uniform)
-        const U4 P0 = philox10(4u * v, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
-        const U4 P1 = philox10(4u * v + 1u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
-        const U4 P2 = philox10(4u * v + 2u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+        const U4 P0 = philox10(4u * v, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
+        const U4 P1 = philox10(4u * v + 1u, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
+        const U4 P2 = philox10(4u * v + 2u, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
         const uint32_t pl[12] = {P0.x, P0.y, P0.z, P0.w, P1.x, P1.y, P1.z, P1.w, P2.x, P2.y, P2.z, P2.w};
 #pragma unroll
         for (int q = 0; q < 12; ++q) {
@@ -304,7 +307,7 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_
 #pragma unroll
         for (int kk = 3; kk < 4; ++kk) {
             if (!__any(eq != 0u)) break;
-            const U4 P = philox10(4u * v + (uint32_t)kk, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+            const U4 P = philox10(4u * v + (uint32_t)kk, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
             const uint32_t pq[4] = {P.x, P.y, P.z, P.w};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -320,7 +323,7 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_
             const int b = __builtin_ctz(tie);
             tie &= tie - 1u;
             const uint32_t q = 32u * v + (uint32_t)b;
-            const U4 P = philox10(q >> 3, ctr1, j, kStreamSweepLow, a.key0, a.key1);
+            const U4 P = philox10(q >> 3, ctr1, j, a.tag | kStreamSweepLow, a.key0, a.key1);
             const uint32_t word = pick(P, (q >> 1) & 3u);
             const uint32_t lo = (q & 1u) ? (word & 0xFFFFu) : (word >> 16);
             const uint32_t tl = ((cls1 >> b) & 1u) ? a.t2l : a.t4l;
@@ -366,9 +369,9 @@ __device__ __forceinline__ uint32_t heatbath_mask(uint32_t w, const Nb& n, uint3
     const HbClass c = hb_classes(w, n);
     uint32_t eq = ~c.zero;
     // blocks 0, 1 and 2 together (three independent chains), as in accept_mask
-    const U4 P0 = philox10(4u * v, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
-    const U4 P1 = philox10(4u * v + 1u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
-    const U4 P2 = philox10(4u * v + 2u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+    const U4 P0 = philox10(4u * v, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
+    const U4 P1 = philox10(4u * v + 1u, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
+    const U4 P2 = philox10(4u * v + 2u, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
     const uint32_t pl[12] = {P0.x, P0.y, P0.z, P0.w, P1.x, P1.y, P1.z, P1.w, P2.x, P2.y, P2.z, P2.w};
     uint32_t acc = c.zero & ~pl[0];  // U_0 = 2^31: x < U_0 iff its top bit is 0
 #pragma unroll
@@ -380,7 +383,7 @@ __device__ __forceinline__ uint32_t heatbath_mask(uint32_t w, const Nb& n, uint3
 #pragma unroll
     for (int kk = 3; kk < 4; ++kk) {
         if (!__any(eq != 0u)) break;
-        const U4 P = philox10(4u * v + (uint32_t)kk, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+        const U4 P = philox10(4u * v + (uint32_t)kk, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
         const uint32_t pq[4] = {P.x, P.y, P.z, P.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -395,7 +398,7 @@ __device__ __forceinline__ uint32_t heatbath_mask(uint32_t w, const Nb& n, uint3
             const int b = __builtin_ctz(tie);
             tie &= tie - 1u;
             const uint32_t q = 32u * v + (uint32_t)b;
-            const U4 P = philox10(q >> 3, ctr1, j, kStreamSweepLow, a.key0, a.key1);
+            const U4 P = philox10(q >> 3, ctr1, j, a.tag | kStreamSweepLow, a.key0, a.key1);
             const uint32_t word = pick(P, (q >> 1) & 3u);
             uint32_t lo = (q & 1u) ? (word & 0xFFFFu) : (word >> 16);
             if ((c.neg >> b) & 1u) lo ^= 0xFFFFu;
@@ -404,6 +407,73 @@ __device__ __forceinline__ uint32_t heatbath_mask(uint32_t w, const Nb& n, uint3
         }
     }
     return acc ^ c.neg;
+}
+
+// In-line LCG variant of the multi-spin-coded sweep (Sec. 4): the generator
+// r' = A r + C mod 2^32 (A = 1664525, C = 1013904223), seeded once per word
+// and update by the base generator, supplies the 32 uniforms of the word.
+// Site b takes the (b+1)-th output after the seed r_0, written in closed form
+// as r_{b+1} = A^{b+1} r_0 + C (A^b + ... + 1) mod 2^32, so the 32 outputs
+// are independent multiply-adds instead of a chain.
+constexpr uint32_t kLcgA = 1664525u;
+constexpr uint32_t kLcgC = 1013904223u;
+
+constexpr uint32_t lcg_mul(int n)  // A^n mod 2^32
+{
+    uint32_t m = 1u;
+    for (int i = 0; i < n; ++i) m *= kLcgA;
+    return m;
+}
+
+constexpr uint32_t lcg_add(int n)  // C (A^{n-1} + ... + A + 1) mod 2^32
+{
+    uint32_t c = 0u;
+    for (int i = 0; i < n; ++i) c = c * kLcgA + kLcgC;
+    return c;
+}
+
+// acc = 2 acc + [x <= t]: the comparison writes a lane mask that the add
+// takes as its carry-in (two VALU instructions; the compiler's own form is a
+// compare, a select and a shift-or).  Arithmetic only, no memory access.
+__device__ __forceinline__ uint32_t shift_in_le(uint32_t acc, uint32_t x, uint32_t t)
+{
+    uint64_t le, carry;
+    __asm__("v_cmp_ge_u32_e64 %1, %4, %3\n\t"
+            "v_addc_co_u32_e64 %0, %2, %0, %0, %1"
+            : "+v"(acc), "=&s"(le), "=&s"(carry)
+            : "v"(x), "s"(t));
+    return acc;
+}
+
+// Metropolis acceptance mask of one 32-site word whose uniforms are the LCG
+// outputs after `seed`: a site flips if k <= 0, else if its uniform x is below
+// T_2 (one anti-aligned neighbour) or T_4 (none), i.e. x <= T - 1 (T >= 1).
+__device__ __forceinline__ uint32_t lcg_accept_mask(uint32_t w, const Nb& n, uint32_t seed, const SweepArgs& a)
+{
+    const uint32_t d1 = w ^ n.up, d2 = w ^ n.dn, d3 = w ^ n.same, d4 = w ^ n.side;
+    const uint32_t o12 = d1 | d2, a12 = d1 & d2, o34 = d3 | d4, a34 = d3 & d4;
+    const uint32_t ge2 = a12 | a34 | (o12 & o34);
+    const uint32_t any = o12 | o34;
+    // T - 1 in 32 bits (T = 2^32 gives 2^32 - 1)
+    const uint32_t t2m1 = (a.t2h << 16) + a.t2l - 1u;
+    const uint32_t t4m1 = (a.t4h << 16) + a.t4l - 1u;
+    uint32_t m2 = 0u, m4 = 0u;
+#pragma unroll
+    for (int b = 31; b >= 0; --b) {
+        const uint32_t x = (uint32_t)((uint64_t)lcg_mul(b + 1) * seed + (uint64_t)lcg_add(b + 1));
+        m2 = shift_in_le(m2, x, t2m1);
+        m4 = shift_in_le(m4, x, t4m1);
+    }
+    return ge2 | (any & ~ge2 & m2) | (~any & m4);
+}
+
+// One colour of the LCG sweep for the lane's one word (register path).
+template <int L, int C>
+__device__ __forceinline__ void half_sweep_lcg(uint32_t (&own)[1], const uint32_t (&oth)[1], int lane, int gl,
+                                               uint32_t seed, const SweepArgs& a)
+{
+    const Neighbours<L, C> nb(oth, lane, gl);
+    own[0] ^= lcg_accept_mask(own[0], nb.get(oth, 0), seed, a);
 }
 
 template <int L, int C, bool HB>
@@ -468,12 +538,14 @@ __device__ __forceinline__ void decide8_group(uint32_t (&w)[NG], const Nb (&n)[N
         }
         need |= eq[g];
     }
-    if (__any(need != 0u)) {
+    // heat-bath draws for every site: its k = 0 sites are decided by plane 0
+    // even when no site of the wave is left for the later planes
+    if (HB || __any(need != 0u)) {
         uint32_t pl[NG][8];
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
-            const U4 P0 = philox10u(4u * v[g], ctr1, j, kStreamSweepHigh, a.key0, a.key1);
-            const U4 P1 = philox10u(4u * v[g] + 1u, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+            const U4 P0 = philox10u(4u * v[g], ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
+            const U4 P1 = philox10u(4u * v[g] + 1u, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
             pl[g][0] = P0.x, pl[g][1] = P0.y, pl[g][2] = P0.z, pl[g][3] = P0.w;
             pl[g][4] = P1.x, pl[g][5] = P1.y, pl[g][6] = P1.z, pl[g][7] = P1.w;
             if constexpr (HB) {
@@ -533,14 +605,14 @@ __device__ __forceinline__ bool decide_tail(uint32_t v, uint32_t b, bool k2, boo
     const uint32_t flip = ng ? 0xFFFFu : 0u;
 #pragma unroll
     for (int kk = 2; kk < 4; ++kk) {
-        const U4 P = philox10u(4u * v + (uint32_t)kk, ctr1, j, kStreamSweepHigh, a.key0, a.key1);
+        const U4 P = philox10u(4u * v + (uint32_t)kk, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
         const uint32_t x = ((((P.x >> b) & 1u) << 3) | (((P.y >> b) & 1u) << 2) | (((P.z >> b) & 1u) << 1) |
                             ((P.w >> b) & 1u)) ^ (flip & 15u);
         const uint32_t t = (th >> (12 - 4 * kk)) & 15u;
         if (x != t) return x < t;
     }
     const uint32_t q = 32u * v + b;
-    const U4 P = philox10u(q >> 3, ctr1, j, kStreamSweepLow, a.key0, a.key1);
+    const U4 P = philox10u(q >> 3, ctr1, j, a.tag | kStreamSweepLow, a.key0, a.key1);
     const uint32_t word = pick(P, (q >> 1) & 3u);
     const uint32_t lo = ((q & 1u) ? (word & 0xFFFFu) : (word >> 16)) ^ flip;
     return lo < (k2 ? a.t2l : a.t4l);
@@ -583,13 +655,14 @@ __device__ __forceinline__ uint32_t tie_entry(int s, int lane, uint32_t k2bit, u
 // return).  vj(lane, slot, &v, &j) gives the word and replica of a lane's
 // slot; ng[s] marks the sites that compare the complement of their uniform
 // (heat-bath, k < 0; all zero for Metropolis); extra[s] receives the
-// additional flips of the lane's word s.  If the queue would overflow, every
-// lane decides its own tied sites instead.
+// additional flips of the lane's word s.  If the queue would hold more than
+// min(a.qcap, QCAP) entries, every lane decides its own tied sites instead.
 template <int S, int QCAP, class VJ>
 __device__ __forceinline__ void resolve_ties_wave(const uint32_t (&tie)[S], const uint32_t (&cls1)[S],
                                                   const uint32_t (&ng)[S], int lane, uint32_t ctr1, const SweepArgs& a,
                                                   uint32_t* queue, uint32_t* res, uint32_t (&extra)[S], const VJ& vj)
 {
+    const uint32_t cap = min(a.qcap, (uint32_t)QCAP);
 #pragma unroll
     for (int s = 0; s < S; ++s) extra[s] = 0u;
     uint32_t cnt = 0;
@@ -598,7 +671,7 @@ __device__ __forceinline__ void resolve_ties_wave(const uint32_t (&tie)[S], cons
     uint32_t total;
     uint32_t off = wave_prefix(cnt, lane, &total);
     if (total == 0u) return;
-    if (total > (uint32_t)QCAP) {
+    if (total > cap) {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             uint32_t t = tie[s];
@@ -700,7 +773,7 @@ template <int L>
 __device__ __forceinline__ uint32_t init_word(int c, uint32_t v, uint32_t j, const SweepArgs& a)
 {
     const uint32_t idx = (uint32_t)(c * Geo<L>::NW) + v;
-    return pick(philox10(idx >> 2, 0u, j, kStreamInit, a.key0, a.key1), idx & 3u);
+    return pick(philox10(idx >> 2, 0u, j, a.tag | kStreamInit, a.key0, a.key1), idx & 3u);
 }
 
 // Bytes of one replica in the spin store.
@@ -773,7 +846,9 @@ __device__ __forceinline__ void write_EM(const SweepArgs& a, const LaneInfo& li,
 }
 
 // Register-resident sweep: each lane owns one word per colour (L <= 64).
-template <int L, bool INT8, bool HB>
+// LCG: the in-line LCG variant; the word's seeds for both colours of a sweep
+// come from one Philox block (outputs x and y).
+template <int L, bool INT8, bool HB, bool LCG>
 __device__ __forceinline__ void sweep_regs(const SweepArgs& a, const LaneInfo& li)
 {
     using Gm = Geo<L>;
@@ -790,8 +865,14 @@ __device__ __forceinline__ void sweep_regs(const SweepArgs& a, const LaneInfo& l
     }
     for (int t = 0; t < a.nsweeps; ++t) {
         const uint32_t g = a.g0 + (uint32_t)t;
-        half_sweep<L, 0, HB>(s0, s1, li.lane, li.gl, g, li.j, a);
-        half_sweep<L, 1, HB>(s1, s0, li.lane, li.gl, g, li.j, a);
+        if constexpr (LCG) {
+            const U4 P = philox10(v, g, li.j, a.tag | kStreamLcgSeed, a.key0, a.key1);
+            half_sweep_lcg<L, 0>(s0, s1, li.lane, li.gl, P.x, a);
+            half_sweep_lcg<L, 1>(s1, s0, li.lane, li.gl, P.y, a);
+        } else {
+            half_sweep<L, 0, HB>(s0, s1, li.lane, li.gl, g, li.j, a);
+            half_sweep<L, 1, HB>(s1, s0, li.lane, li.gl, g, li.j, a);
+        }
     }
     const Neighbours<L, 0> nb(s1, li.lane, li.gl);
     const Nb n = nb.get(s1, 0);
@@ -880,8 +961,26 @@ __device__ __forceinline__ void half_sweep_lds(const LdsRep<L>& rep, int gl, uin
     wave_lds_sync();
 }
 
+// One colour of an LCG sweep on the LDS path: every word of the lane in turn,
+// its seed from the word's Philox block of this sweep (x: colour 0, y:
+// colour 1).  The uniforms are whole 32-bit numbers, so there are no ties.
+template <int L, int C>
+__device__ __forceinline__ void half_sweep_lds_lcg(const LdsRep<L>& rep, int gl, uint32_t g, uint32_t j,
+                                                   const SweepArgs& a)
+{
+    using Gm = Geo<L>;
+#pragma unroll 1
+    for (int k = 0; k < Gm::K; ++k) {
+        const Nb n = rep.template nb<C>(k, gl);
+        const uint32_t w = rep.at(C, k, gl);
+        const U4 P = philox10u((uint32_t)(gl * Gm::K + k), g, j, a.tag | kStreamLcgSeed, a.key0, a.key1);
+        rep.at(C, k, gl) = w ^ lcg_accept_mask(w, n, C == 0 ? P.x : P.y, a);
+    }
+    wave_lds_sync();
+}
+
 // The wave's LDS: replica [2][NW], then the tie queue and the slot results.
-template <int L, bool INT8, bool HB>
+template <int L, bool INT8, bool HB, bool LCG>
 __device__ __forceinline__ void sweep_lds(const SweepArgs& a, uint32_t j, uint32_t* lds)
 {
     using Gm = Geo<L>;
@@ -909,8 +1008,13 @@ __device__ __forceinline__ void sweep_lds(const SweepArgs& a, uint32_t j, uint32
     wave_lds_sync();
     for (int t = 0; t < a.nsweeps; ++t) {
         const uint32_t g = a.g0 + (uint32_t)t;
-        half_sweep_lds<L, 0, HB>(rep, gl, g, j, a, queue, res);
-        half_sweep_lds<L, 1, HB>(rep, gl, g, j, a, queue, res);
+        if constexpr (LCG) {
+            half_sweep_lds_lcg<L, 0>(rep, gl, g, j, a);
+            half_sweep_lds_lcg<L, 1>(rep, gl, g, j, a);
+        } else {
+            half_sweep_lds<L, 0, HB>(rep, gl, g, j, a, queue, res);
+            half_sweep_lds<L, 1, HB>(rep, gl, g, j, a, queue, res);
+        }
     }
     uint32_t anti = 0, downs = 0;
 #pragma unroll 1
@@ -950,8 +1054,9 @@ constexpr int sweep_block()
 // holding waves [wave0, wave0 + wpb) of a run (wpb = blockDim.x / 64); lds is
 // the block's Geo<L>::lds_words(wpb) words (none on the register path).
 // Waves share no barrier: each returns as soon as it holds no replica.  HB
-// selects the heat-bath update instead of Metropolis.
-template <int L, bool INT8, bool HB>
+// selects the heat-bath update instead of Metropolis; LCG the in-line LCG
+// variant of the Metropolis sweep.
+template <int L, bool INT8, bool HB, bool LCG = false>
 __device__ __forceinline__ void sweep_waves(const SweepArgs& a, int wave0, int wpb, uint32_t* lds)
 {
     using Gm = Geo<L>;
@@ -966,9 +1071,10 @@ __device__ __forceinline__ void sweep_waves(const SweepArgs& a, int wave0, int w
         if constexpr (Gm::REPW == 1) jj = __builtin_amdgcn_readfirstlane(jj);
         li.j = (uint32_t)jj;
         li.valid = jj < a.n_rep;
-        sweep_regs<L, INT8, HB>(a, li);
+        sweep_regs<L, INT8, HB, LCG>(a, li);
     } else {
-        sweep_lds<L, INT8, HB>(a, (uint32_t)__builtin_amdgcn_readfirstlane(wave), lds + wib * Gm::WAVE_LDS_WORDS);
+        sweep_lds<L, INT8, HB, LCG>(a, (uint32_t)__builtin_amdgcn_readfirstlane(wave),
+                                    lds + wib * Gm::WAVE_LDS_WORDS);
     }
 }
 

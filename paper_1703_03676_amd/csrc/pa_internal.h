@@ -41,9 +41,12 @@ struct SweepArgs {
     int32_t n_rep;          // number of replicas to process
     int32_t nsweeps;
     uint32_t g0;            // global sweep number of the first sweep
-    uint32_t key0, key1;    // Philox key
+    uint32_t key0, key1;    // Philox key: the run's seed
+    uint32_t tag;           // 16 * run number: counter word 3 without the stream number
     uint32_t t2h, t2l;      // threshold T_2 = t2h * 2^16 + t2l  (t2h <= 65536)
     uint32_t t4h, t4l;      // threshold T_4  (heat-bath: U_2, U_4, each <= 2^31)
+    uint32_t qcap;          // LDS path: tie-queue entries a wave may use before every lane decides its
+                            // own ties (values at or above the queue size: the whole queue)
     int32_t init;           // 1: draw the initial state instead of loading spins
     const uint32_t* n_dev;  // if set: the population size is min(*n_dev, n_rep), read on the device
     const uint8_t* src;     // with parent: replica j starts from replica parent[j] of this store
@@ -51,5 +54,12 @@ struct SweepArgs {
 };
 
 constexpr int kBlock = 256;     // threads per block of the population kernels
+
+// Update rule of the sweep kernels.
+enum Update : int {
+    kMetropolis = 0,  // Metropolis with the bit-sliced Philox uniforms
+    kHeatbath = 1,    // heat-bath with the same uniforms
+    kLcg = 2          // Metropolis with uniforms from the in-line LCG variant
+};
 
 }  // namespace pa

@@ -97,14 +97,14 @@ __global__ void fill_u32_kernel(uint32_t* p, uint32_t value, size_t n)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void counts_kernel(const int32_t* __restrict__ E, int32_t n, int32_t N,
                                                         int32_t bmin, int32_t nwin, const uint32_t* __restrict__ tbl,
-                                                        uint32_t step, uint32_t key0, uint32_t key1,
+                                                        uint32_t step, uint32_t key0, uint32_t key1, uint32_t tag,
                                                         uint32_t* __restrict__ counts, uint32_t* __restrict__ bsum)
 {
     const int j = (int)(blockIdx.x * kBlock + threadIdx.x);
     uint32_t c = 0;
     if (j < n) {
         const int b = ((E[j] + 2 * N) >> 2) - bmin;
-        const uint32_t x = pick(philox10((uint32_t)j >> 2, step, 0u, kStreamResample, key0, key1), (uint32_t)j & 3u);
+        const uint32_t x = pick(philox10((uint32_t)j >> 2, step, 0u, tag | kStreamResample, key0, key1), (uint32_t)j & 3u);
         if (b >= 0 && b < nwin) {  // always true for the population the tables were built from
             const uint32_t base = tbl[2 * b], thr = tbl[2 * b + 1];
             c = base + (x <= thr ? 1u : 0u);
@@ -265,12 +265,13 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s)
 }
 
 hipError_t launch_counts(const int32_t* E, int32_t n, int32_t N, int32_t bmin, int32_t nwin, const uint32_t* tbl,
-                         uint32_t step, uint32_t key0, uint32_t key1, uint32_t* counts, uint32_t* bsum, hipStream_t s)
+                         uint32_t step, uint32_t key0, uint32_t key1, uint32_t tag, uint32_t* counts, uint32_t* bsum,
+                         hipStream_t s)
 {
     const int blocks = (n + kBlock - 1) / kBlock;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL(counts_kernel, dim3(blocks), dim3(kBlock), 0, s, E, n, N, bmin, nwin, tbl, step, key0, key1,
-                       counts, bsum);
+                       tag, counts, bsum);
     return hipGetLastError();
 }
 

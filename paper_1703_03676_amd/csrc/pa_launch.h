@@ -6,9 +6,9 @@
 namespace pa {
 
 // Kernel launchers; each returns the launch status.
-// heatbath selects the heat-bath update (thresholds U_2, U_4 in t2*/t4*)
-// instead of Metropolis (T_2, T_4).
-hipError_t launch_sweep(int L, int layout, bool heatbath, const SweepArgs& a, hipStream_t s);
+// `update` (pa::Update) selects Metropolis (thresholds T_2, T_4 in t2*/t4*),
+// heat-bath (U_2, U_4) or the in-line LCG variant of Metropolis.
+hipError_t launch_sweep(int L, int layout, int update, const SweepArgs& a, hipStream_t s);
 // Statistics of a population (after the statistics block and the histogram
 // have been cleared, by launch_stats_reset or launch_scatter): histogram,
 // range, moment sums; parts holds ceil(n / kBlock) partials.  With n_dev the
@@ -22,7 +22,7 @@ hipError_t launch_stats(const int32_t* E, const int32_t* M, int32_t n, const uin
 // bytes) the statistics block and the histogram window [emin, emax] are also
 // written there (bin b at byte 64 + 4 b).
 hipError_t launch_counts(const int32_t* E, int32_t n, int32_t N, int32_t bmin, int32_t nwin, const uint32_t* tbl,
-                         uint32_t step, uint32_t key0, uint32_t key1, uint32_t* counts, uint32_t* bsum,
+                         uint32_t step, uint32_t key0, uint32_t key1, uint32_t tag, uint32_t* counts, uint32_t* bsum,
                          hipStream_t s);
 // Parent indices (children beyond cap are dropped), the total of the counts in
 // st->r_new, and the statistics block and histogram cleared for the next

@@ -13,8 +13,9 @@
 // For L <= 64 the planes stop as soon as no site of the wave is undecided; for
 // L >= 128 a lane decides 8 planes for several words and queues the sites
 // still tied, which the wave then decides one per lane (pa_device.h).  A run
-// created with PA_FLAG_HEATBATH uses the heat-bath update in the same scheme
-// (its own kernel instantiations).
+// created with PA_FLAG_HEATBATH uses the heat-bath update in the same scheme,
+// one created with PA_FLAG_LCG the in-line LCG variant of the multi-spin-coded
+// sweep (Sec. 4), each with its own kernel instantiations.
 #include "pa_device.h"
 #include "pa_launch.h"
 
@@ -23,7 +24,7 @@ namespace {
 
 using namespace pa::dev;
 
-template <int L, bool INT8, bool HB>
+template <int L, bool INT8, int U>
 __global__ __launch_bounds__(sweep_block<L>())
 __attribute__((amdgpu_waves_per_eu(sweep_min_waves<L>(), 8))) void sweep_kernel(SweepArgs a)
 {
@@ -31,38 +32,48 @@ __attribute__((amdgpu_waves_per_eu(sweep_min_waves<L>(), 8))) void sweep_kernel(
     constexpr int WPB = sweep_block<L>() / 64;
     __shared__ uint32_t lds[Gm::lds_words(WPB) > 0 ? Gm::lds_words(WPB) : 1];
     if (a.n_dev) a.n_rep = min(a.n_rep, (int32_t)*a.n_dev);
-    sweep_waves<L, INT8, HB>(a, (int)blockIdx.x * WPB, WPB, lds);
+    sweep_waves<L, INT8, U == kHeatbath, U == kLcg>(a, (int)blockIdx.x * WPB, WPB, lds);
 }
 
-template <int L, bool INT8, bool HB>
+template <int L, bool INT8, int U>
 hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t s)
 {
     using Gm = Geo<L>;
     const int reps_per_block = (sweep_block<L>() / 64) * Gm::RPWV;
     const int blocks = (a.n_rep + reps_per_block - 1) / reps_per_block;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL((sweep_kernel<L, INT8, HB>), dim3(blocks), dim3(sweep_block<L>()), 0, s, a);
+    hipLaunchKernelGGL((sweep_kernel<L, INT8, U>), dim3(blocks), dim3(sweep_block<L>()), 0, s, a);
     return hipGetLastError();
 }
 
-template <int L>
-hipError_t launch_sweep_l(bool i8, bool hb, const SweepArgs& a, hipStream_t s)
+template <int L, bool INT8>
+hipError_t launch_sweep_u(int update, const SweepArgs& a, hipStream_t s)
 {
-    if (hb) return i8 ? launch_sweep_t<L, true, true>(a, s) : launch_sweep_t<L, false, true>(a, s);
-    return i8 ? launch_sweep_t<L, true, false>(a, s) : launch_sweep_t<L, false, false>(a, s);
+    switch (update) {
+    case kMetropolis: return launch_sweep_t<L, INT8, kMetropolis>(a, s);
+    case kHeatbath: return launch_sweep_t<L, INT8, kHeatbath>(a, s);
+    case kLcg: return launch_sweep_t<L, INT8, kLcg>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int L>
+hipError_t launch_sweep_l(bool i8, int update, const SweepArgs& a, hipStream_t s)
+{
+    return i8 ? launch_sweep_u<L, true>(update, a, s) : launch_sweep_u<L, false>(update, a, s);
 }
 
 }  // namespace
 
-hipError_t launch_sweep(int L, int layout, bool heatbath, const SweepArgs& a, hipStream_t s)
+hipError_t launch_sweep(int L, int layout, int update, const SweepArgs& a, hipStream_t s)
 {
     const bool i8 = layout == 0;
     switch (L) {
-    case 16: return launch_sweep_l<16>(i8, heatbath, a, s);
-    case 32: return launch_sweep_l<32>(i8, heatbath, a, s);
-    case 64: return launch_sweep_l<64>(i8, heatbath, a, s);
-    case 128: return launch_sweep_l<128>(i8, heatbath, a, s);
-    case 256: return launch_sweep_l<256>(i8, heatbath, a, s);
+    case 16: return launch_sweep_l<16>(i8, update, a, s);
+    case 32: return launch_sweep_l<32>(i8, update, a, s);
+    case 64: return launch_sweep_l<64>(i8, update, a, s);
+    case 128: return launch_sweep_l<128>(i8, update, a, s);
+    case 256: return launch_sweep_l<256>(i8, update, a, s);
     default: return hipErrorInvalidValue;
     }
 }

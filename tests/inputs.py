@@ -29,3 +29,12 @@ def mixed_spins(R, L, seed):
     rng = np.random.default_rng(seed)
     p = rng.random(R)[:, None, None] * 0.5
     return np.where(rng.random((R, L, L)) < p, -1, 1).astype(np.int8)
+
+
+def structured_spins(R, L, kind):
+    """R copies of one regular pattern: 'cols' s(x, y) = (-1)^x, 'rows'
+    s(x, y) = (-1)^y, 'checker' s(x, y) = (-1)^(x + y), 'up' all +1."""
+    y, x = np.mgrid[0:L, 0:L]
+    pattern = {"cols": x % 2, "rows": y % 2, "checker": (x + y) % 2, "up": np.zeros((L, L), int)}[kind]
+    one = np.where(pattern == 1, -1, 1).astype(np.int8)
+    return np.broadcast_to(one, (R, L, L)).copy()

@@ -45,8 +45,13 @@ def test_workspace_bytes_validation():
                 pa.make_params(16, 10, 1, layout=7)):
         assert pa.workspace_bytes(bad) == 0
     bad_flags = pa.make_params(16, 10, 1)
-    bad_flags.flags = 4
-    assert pa.workspace_bytes(bad_flags) == 0
+    for flags in (8, pa.PA_FLAG_HEATBATH | pa.PA_FLAG_LCG):
+        bad_flags.flags = flags
+        assert pa.workspace_bytes(bad_flags) == 0
+    bad_run = pa.make_params(16, 10, 1, run_id=1 << 28)
+    assert pa.workspace_bytes(bad_run) == 0
+    assert pa.workspace_bytes(pa.make_params(16, 10, 1, run_id=(1 << 28) - 1)) > 0
+    assert pa.workspace_bytes(pa.make_params(64, 20000, 1, lcg=True)) == n_bits
     # the heat-bath update needs no extra device memory
     assert pa.workspace_bytes(pa.make_params(64, 20000, 1, heatbath=True)) == n_bits
     assert pa.workspace_bytes(pa.make_params(64, 20000, 1, heatbath=True, mhr=True)) == \

@@ -39,6 +39,7 @@ RUNS = [
     dict(L=128, R=6, seed=15, layout="bits"),
     dict(L=256, R=3, seed=16, layout="int8"),
     dict(L=32, R=150, seed=17, layout="bits"),
+    dict(L=128, R=5, seed=18, layout="int8", heatbath=True),
 ]
 SCHED = [
     dict(beta_f=1.0, dbeta=0.05, theta=5, mode="fixed"),
@@ -48,11 +49,23 @@ SCHED = [
     dict(beta_f=0.6, dbeta=0.2, theta=1, mode="fixed"),
     dict(beta_f=0.5, dbeta=0.25, theta=1, mode="fixed"),
     dict(beta_f=0.9, alpha_star=0.9, theta=2, mode="adaptive"),
+    dict(beta_f=0.6, dbeta=0.15, theta=3, mode="fixed"),
 ]
 
 
+_TRACES = {}
+
+
 def _oracle_trace(spec, sched):
-    o = oracle.Run(spec["L"], spec["R"], seed=spec["seed"], run_id=spec.get("run_id", 0))
+    key = (tuple(sorted(spec.items())), tuple(sorted(sched.items())))
+    if key not in _TRACES:
+        _TRACES[key] = _make_oracle_trace(spec, sched)
+    return _TRACES[key]
+
+
+def _make_oracle_trace(spec, sched):
+    o = oracle.Run(spec["L"], spec["R"], seed=spec["seed"], run_id=spec.get("run_id", 0),
+                   heatbath=spec.get("heatbath", False))
     o.init()
     trace = [o.measure()]
     i = 0
@@ -70,9 +83,18 @@ def _oracle_trace(spec, sched):
     return o, trace
 
 
-def test_mixed_batch_matches_independent_oracle_runs():
-    print("case mixed batch", flush=True)
-    b = pa.Batch(RUNS, SCHED)
+@pytest.mark.parametrize("wpb,qcap", [(0, None), (1, None), (2, None), (4, None), (8, None), (2, 0), (4, 8)])
+def test_mixed_batch_matches_independent_oracle_runs(wpb, qcap):
+    # every sweep shape (waves per block; L = 256 takes at most 4, the largest
+    # that fits its LDS) and, with qcap, the overflow route of the LDS path's
+    # tie queue
+    print("case mixed batch wpb=%d qcap=%s" % (wpb, qcap), flush=True)
+    b = pa.Batch(RUNS, SCHED, waves_per_block=wpb)
+    if wpb:
+        for r, spec in enumerate(RUNS):
+            assert b.waves_per_block(r) == (min(wpb, 4) if spec["L"] == 256 else wpb)
+    if qcap is not None:
+        b.set_tie_queue_cap(qcap)
     b.run()
     for r, (spec, sc) in enumerate(zip(RUNS, SCHED)):
         print("  run %d L=%d" % (r, spec["L"]), flush=True)

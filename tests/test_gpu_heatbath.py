@@ -84,6 +84,30 @@ def test_heatbath_many_sweeps_exercise_ties(L, R, nsw, layout):
     _same_population(g, o)
 
 
+@pytest.mark.parametrize("heatbath", [True, False])
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("L", [16, 32, 64, 128, 256])
+@pytest.mark.parametrize("kind", ["cols", "rows", "checker", "up"])
+def test_structured_populations_match_oracle(kind, L, layout, heatbath):
+    # regular patterns put every site of a replica in one class: stripes
+    # have k = 0 everywhere (heat-bath decides them by the top bit of the
+    # uniform, Metropolis flips them without one), the checkerboard k = -4,
+    # all-up k = 4; on the LDS path one wave holds one replica, so no site of
+    # the wave needs the later planes
+    R = 4 if L >= 128 else 40
+    print("case structured %s L=%d layout=%s hb=%d" % (kind, L, layout, heatbath), flush=True)
+    spins = inputs.structured_spins(R, L, kind)
+    for nsw in (1, 2):
+        g = pa.Run(L, R, seed=21, layout=layout, heatbath=heatbath)
+        g.upload_population(spins, step=1, sweeps=4, beta=0.3)
+        o = oracle.Run(L, R, seed=21, heatbath=heatbath)
+        o.set_population(spins, step=1, sweeps=4, beta=0.3)
+        g.sweep(nsw)
+        o.sweep(nsw)
+        _same_population(g, o)
+        g.close()
+
+
 def test_metropolis_and_heatbath_runs_differ_on_the_gpu():
     spins = inputs.random_spins(9, 64, seed=2)
     runs = []

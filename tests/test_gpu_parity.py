@@ -97,9 +97,11 @@ def test_many_sweeps_exercise_ties(layout):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
-@pytest.mark.parametrize("L", [16, 64, 256])
+@pytest.mark.parametrize("L", [16, 32, 64, 128, 256])
 def test_resample_matches_oracle(L, layout):
-    R = {16: 1500, 64: 700, 256: 40}[L]
+    # replica sizes from 32 B to 64 KiB: every team width of the copy kernel
+    # (16, 64 and 256 threads per child; 64 at L = 32 int8 and L = 128 bits)
+    R = {16: 1500, 32: 900, 64: 700, 128: 120, 256: 40}[L]
     print("case resample L=%d layout=%s" % (L, layout), flush=True)
     spins = inputs.mixed_spins(R, L, seed=3)
     g = pa.Run(L, R, seed=5, layout=layout)
@@ -116,6 +118,49 @@ def test_resample_matches_oracle(L, layout):
         _same_population(g, o)
         st = g.state()
         assert st["lnZ"] == o.lnZ and st["step"] == o.step and st["beta"] == o.beta
+
+
+@pytest.mark.parametrize("heatbath", [False, True])
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("L,R,nsw", [(128, 6, 6), (256, 3, 3)])
+@pytest.mark.parametrize("cap", [0, 8])
+def test_tie_queue_overflow_route(cap, L, R, nsw, layout, heatbath):
+    # a wave's tie queue limited to `cap` entries: the chunks with more tied
+    # sites than that (every chunk with a tie at cap 0) are decided lane by
+    # lane instead of through the queue; the chain is the same
+    print("case tie queue cap=%d L=%d layout=%s hb=%d" % (cap, L, layout, heatbath), flush=True)
+    spins = inputs.mixed_spins(R, L, seed=L + 7)
+    g = pa.Run(L, R, seed=19, layout=layout, heatbath=heatbath)
+    g.set_tie_queue_cap(cap)
+    g.upload_population(spins, step=2, sweeps=5, beta=0.55)
+    o = oracle.Run(L, R, seed=19, heatbath=heatbath)
+    o.set_population(spins, step=2, sweeps=5, beta=0.55)
+    g.sweep(nsw)
+    o.sweep(nsw)
+    _same_population(g, o)
+    g.set_tie_queue_cap(256)
+    g.sweep(1)
+    o.sweep(1)
+    _same_population(g, o)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("L,R", [(32, 700), (128, 60)])
+def test_anneal_without_sweeps(L, R, layout):
+    # theta = 0: pa_anneal resamples with the separate copy kernel (no sweep
+    # to fuse it into) and measures; compared with the oracle step by step
+    print("case anneal theta=0 L=%d layout=%s" % (L, layout), flush=True)
+    spins = inputs.mixed_spins(R, L, seed=4)
+    g = pa.Run(L, R, seed=8, layout=layout)
+    g.upload_population(spins, step=0, sweeps=0, beta=0.0, lnZ=float(L * L) * np.log(2.0))
+    o = oracle.Run(L, R, seed=8)
+    o.set_population(spins, step=0, sweeps=0, beta=0.0, lnZ=float(L * L) * np.log(2.0))
+    res = g.anneal(beta_f=0.3, dbeta=0.05, theta=0)
+    assert len(res) == 6
+    for i, go in enumerate(res, start=1):
+        o.resample(min(i * 0.05, 0.3) if i < 6 else 0.3)
+        _same_obs(go, o.measure())
+    _same_population(g, o)
 
 
 def test_resample_many_blocks_uses_the_block_scan():

@@ -3,6 +3,7 @@
 Each case copies the oracle's C source, plants one plausible mistake (a wrong
 constant, sign, index, operand or comparison), builds it on the CPU and runs a
 fast battery of the same pins the oracle tests use: published Philox vectors,
+independence of the sites of one word and of runs in the random streams,
 the exact Boltzmann distribution and exact free energy at L = 4, closed forms at
 beta = 0, the heat-bath flip law per class, resampling normalisation and order, multi-histogram reweighting and
 the adaptive-step postcondition.  The unmodified source must pass the battery
@@ -17,6 +18,7 @@ import pytest
 import exact
 import inputs
 import oracle
+import stream_pins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "pa_oracle.c")
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
@@ -33,7 +35,7 @@ MUTANTS = {
     "neighbour_index": ("s[y * L + (x + L - 1) % L]", "s[y * L + (x + 1) % L]"),
     "energy_bookkeeping": ("r->E[j] += 2 * k;", "r->E[j] += k;"),
     "magnetisation_bookkeeping": ("r->M[j] -= 2 * si;", "r->M[j] += 2 * si;"),
-    "acceptance_direction": ("planes) < T);", "planes) >= T);"),
+    "acceptance_direction": ("flip = ((uint64_t)x < T);", "flip = ((uint64_t)x >= T);"),
     "weight_sign": ("w[b] = exp(-(dbeta * d));", "w[b] = exp(dbeta * d);"),
     "tau_normalisation": ("double tau = ((double)r->R * w[b]) / W;", "double tau = ((double)r->Rcur * w[b]) / W;"),
     "count_comparison": ("(x <= thr[b] ? 1u : 0u)", "(x > thr[b] ? 1u : 0u)"),
@@ -50,8 +52,22 @@ MUTANTS = {
     "hb_zero_k": ("if (k == 0) return two32 / 2;", "if (k == 0) return two32;"),
     "hb_exponent_sign": ("1.0 / (1.0 + exp(4.0 * beta))", "1.0 / (1.0 + exp(-4.0 * beta))"),
     "hb_exponent_scale": ("1.0 / (1.0 + exp(8.0 * beta))", "1.0 / (1.0 + exp(4.0 * beta))"),
-    "hb_direction": ("flip = ((uint64_t)site_uniform(r, g, c, slot, q, planes) < U);",
-                     "flip = ((uint64_t)site_uniform(r, g, c, slot, q, planes) > U);"),
+    "hb_direction": ("flip = ((uint64_t)x < U);", "flip = ((uint64_t)x > U);"),
+    # stream mapping: sites q and q + 16 share their high 16 bits
+    "plane_alias": ("int bit = q & 31;", "int bit = q & 15;"),
+    # stream mapping: sites q and q ^ 1 share one half of a SWEEP-LOW word
+    "low_half_shared": ("uint32_t lo = (q & 1) ? (low_word & 0xFFFFu) : (low_word >> 16);",
+                        "uint32_t lo = low_word >> 16;"),
+    # stream mapping: the run number left out of the counters
+    "run_tag_dropped": ("r->tag = run_id << 4;", "r->tag = 0;"),
+    # in-line LCG variant (Sec. 4): multiplier, state update, seed counters
+    "lcg_multiplier": ("#define LCG_A 1664525u", "#define LCG_A 1u"),
+    "lcg_state_frozen": ("        x = lcg_next(x);\n        out[b] = x;", "        out[b] = lcg_next(x);"),
+    "lcg_seed_colour": ("r->tag | 4, c);", "r->tag | 4, 0);"),
+    "lcg_seed_sweep": ("(uint32_t)v, (uint32_t)g, (uint32_t)j, r->tag | 4", "(uint32_t)v, 0u, (uint32_t)j, r->tag | 4"),
+    # the run number xored into the key (seed_hi = 1, run 0 == seed_hi = 0, run 1)
+    "run_in_key": ("r->key1 = (uint32_t)(seed >> 32);\n    r->tag = run_id << 4;",
+                   "r->key1 = (uint32_t)(seed >> 32) ^ run_id;\n    r->tag = 0;"),
 }
 
 
@@ -69,6 +85,14 @@ def battery(lib, full=False):
             if line.strip() and not line.startswith("#"):
                 v = [int(x, 16) for x in line.split()]
                 _check(oracle.philox(v[0:4], v[4:6], lib) == v[6:10], "philox_kat", failures)
+
+        # random streams: independent sites within a word, runs keyed apart
+        _check(stream_pins.site_pairs_independent(lib), "site_pairs_independent", failures)
+        _check(stream_pins.site_uniforms_independent(lib), "site_uniforms_independent", failures)
+        _check(stream_pins.runs_have_own_streams(lib), "runs_have_own_streams", failures)
+        _check(stream_pins.uniforms_distinct_across_updates(lib), "distinct_updates", failures)
+        _check(stream_pins.site_pairs_independent(lib, lcg=True), "lcg_site_pairs_independent", failures)
+        _check(stream_pins.uniforms_distinct_across_updates(lib, lcg=True), "lcg_distinct_updates", failures)
 
         # beta = 0 closed forms (independent spins)
         r = oracle.Run(8, 4000, seed=11, lib_=lib)
@@ -101,6 +125,19 @@ def battery(lib, full=False):
             chi2 = ((cnt[keep] - m[keep]) ** 2 / m[keep]).sum()
             dof = keep.sum() - 1
             _check(chi2 < dof + 6 * np.sqrt(2 * dof), "boltzmann_L4", failures)
+
+        # the in-line LCG variant reaches the same distribution at L = 4
+        r = oracle.Run(4, 4000, seed=25, lib_=lib, lcg=True)
+        r.set_population(inputs.random_spins(4000, 4, 9), beta=0.44)
+        r.sweep(40)
+        _, E, _ = r.get_population()
+        ex = exact.brute_observables(4, 0.44)
+        cnt = np.array([(E == e).sum() for e in ex["Ev"]])
+        m = ex["pE"] * cnt.sum()
+        keep = m > 5
+        chi2 = ((cnt[keep] - m[keep]) ** 2 / m[keep]).sum()
+        dof = keep.sum() - 1
+        _check(chi2 < dof + 6 * np.sqrt(2 * dof), "lcg_boltzmann_L4", failures)
 
         # heat-bath: flip frequency of each class k of colour 0 (updated first,
         # against the initial neighbours) and the Boltzmann distribution at L = 4

@@ -7,6 +7,7 @@ import pytest
 import exact
 import inputs
 import oracle
+import stream_pins
 
 
 def _chi2(counts, probs):
@@ -55,6 +56,28 @@ def test_init_reproducible_and_keyed():
     c.init()
     assert np.array_equal(a.get_population()[0], b.get_population()[0])
     assert not np.array_equal(a.get_population()[0], c.get_population()[0])
+
+
+def test_sites_of_one_word_decide_independently():
+    # one uniform per spin update (Sec. 3): the colour-0 word of an all-up
+    # 8 x 8 lattice (k = 4 at every site) flips each site with T_4 / 2^32,
+    # and the pairs (q, q + 16) and (q, q ^ 1) flip independently
+    f, p = stream_pins.colour0_word_flips(oracle.lib())
+    assert abs(f.mean() - p) < 5 * np.sqrt(p * (1 - p) / f.size)
+    assert stream_pins.chi2_independent(f[:, :16].ravel(), f[:, 16:].ravel()) < 25.0
+    assert stream_pins.chi2_independent(f[:, 0::2].ravel(), f[:, 1::2].ravel()) < 25.0
+    assert stream_pins.site_pairs_independent(oracle.lib())
+
+
+def test_site_uniforms_share_no_halves():
+    assert stream_pins.site_uniforms_independent(oracle.lib())
+
+
+def test_runs_have_streams_of_their_own():
+    # (seed_hi = 1, run 0) and (seed_hi = 0, run 1) are different runs
+    assert stream_pins.runs_have_own_streams(oracle.lib())
+    with pytest.raises(ValueError):
+        oracle.Run(8, 10, seed=1, run_id=1 << 28)
 
 
 def test_incremental_bookkeeping_matches_recount():
@@ -116,3 +139,21 @@ def test_metropolis_samples_boltzmann_L4(beta):
     cM = np.array([(aM == a).sum() for a in absv])
     chi2, dof = _chi2(cM, pabs)
     assert chi2 < dof + 6 * np.sqrt(2 * dof), (chi2, dof)
+
+
+@pytest.mark.parametrize("heatbath", [False, True])
+def test_threads_over_replicas_give_the_same_run(heatbath):
+    # the OpenMP loop over replicas (timing only) changes nothing
+    pops = []
+    for threads in (1, 4):
+        r = oracle.Run(16, 301, seed=9, heatbath=heatbath)
+        r.set_threads(threads)
+        r.init()
+        r.resample(0.2)
+        r.sweep(3)
+        r.resample(0.45)
+        r.sweep(2)
+        pops.append((r.get_population(), r.measure()))
+    (a, oa), (b, ob) = pops
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    assert oa == ob
