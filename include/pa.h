@@ -360,6 +360,13 @@ pa_status pa_batch_training_pairs(const pa_batch* b, float* x, float* t, int32_t
  * is exp(prop - x[1]). */
 pa_status pa_batch_features(const pa_batch* b, int32_t run, float* x, int32_t* valid, float* prop);
 
+/* Cost of choosing one run's temperatures so far: the number of overlap
+ * evaluations alpha(beta_i, beta') of Sec. 2.3 (a bisection makes 51 per step
+ * unless beta_f is reached at once, an accepted learned proposal 1, a
+ * rejected one 1 before its bisection) and the host seconds spent choosing
+ * (fixed and follower runs: 0). */
+pa_status pa_batch_choice_stats(const pa_batch* b, int32_t run, int64_t* alpha_evals, double* host_seconds);
+
 /* Learned mode: proposals made and accepted by the exact overlap test. */
 pa_status pa_batch_learned_stats(const pa_batch* b, int32_t run, int32_t* proposals, int32_t* accepted);
 

@@ -123,6 +123,7 @@ SIGNATURES = {
     "pa_batch_training_pairs": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int32, _P(ctypes.c_int32)]),
     "pa_batch_features": (ctypes.c_int, [_vp, ctypes.c_int32, _vp, _P(ctypes.c_int32), _P(ctypes.c_float)]),
     "pa_batch_learned_stats": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int32), _P(ctypes.c_int32)]),
+    "pa_batch_choice_stats": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int64), _P(ctypes.c_double)]),
     "pa_mlp_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
     "pa_mlp_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_uint64, _vp, ctypes.c_size_t, _vp, _P(_vp)]),
     "pa_mlp_set_params": (ctypes.c_int, [_vp, _vp, _vp]),
@@ -450,6 +451,12 @@ class Batch:
 
     def set_tie_queue_cap(self, cap):
         _check(lib().pa_batch_set_tie_queue_cap(self.h, int(cap)))
+
+    def choice_stats(self, run):
+        """(overlap evaluations, host seconds) spent choosing run's temperatures."""
+        n, t = ctypes.c_int64(), ctypes.c_double()
+        _check(lib().pa_batch_choice_stats(self.h, int(run), ctypes.byref(n), ctypes.byref(t)))
+        return n.value, t.value
 
     def learned_stats(self, run):
         p, a = ctypes.c_int32(), ctypes.c_int32()

@@ -20,6 +20,7 @@
 // store) by timing the candidates on the batch's own spare buffers at start-up.
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <condition_variable>
 #include <cstdio>
@@ -610,6 +611,8 @@ struct RunHost {
     FeatDev feat;
     double last_dbeta = 0.0;
     int32_t proposals = 0, accepted = 0;
+    int64_t alpha_evals = 0;   // overlap evaluations made to choose the temperatures
+    double choose_s = 0.0;     // host seconds spent choosing them
     std::vector<float> pair_x, pair_t;  // (features, ln(step sigma_E)) from the bisection
 };
 
@@ -838,6 +841,7 @@ bool choose_beta(RunHost& h, const host::Hist& hw, bool model_set, double* beta_
             const double bp = std::min(h.beta + d, s.beta_f);
             if (bp > h.beta) {
                 const double a = host::overlap(hw, h.p.R, h.R_cur, bp - h.beta, h.w);
+                h.alpha_evals += 1;
                 h.proposals += 1;
                 if (std::fabs(a - s.alpha_star) <= s.alpha_tol || (bp == s.beta_f && a >= s.alpha_star)) {
                     h.accepted += 1;
@@ -847,8 +851,8 @@ bool choose_beta(RunHost& h, const host::Hist& hw, bool model_set, double* beta_
             }
         }
     }
-    double a = 0.0;
-    if (!host::adapt_beta(hw, h.p.R, h.R_cur, h.beta, s.beta_f, s.alpha_star, beta_next, &a, h.w)) {
+    if (!host::adapt_beta(hw, h.p.R, h.R_cur, h.beta, s.beta_f, s.alpha_star, beta_next, nullptr, h.w,
+                          &h.alpha_evals)) {
         h.status = PA_EINVAL;
         return false;
     }
@@ -1089,7 +1093,10 @@ pa_status pa_batch_step(pa_batch* b, int32_t* n_active)
         if (h.finished || h.status != PA_OK || h.sched.mode == PA_STEP_FOLLOW) return;
         const host::Hist hw = host::hist_window(h.h_hist, h.h_stats, h.p.L * h.p.L);
         double bn = 0.0;
-        if (!choose_beta(h, hw, b->model_set, &bn)) return;
+        const auto t0 = std::chrono::steady_clock::now();
+        const bool ok = choose_beta(h, hw, b->model_set, &bn);
+        h.choose_s += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        if (!ok) return;
         h.beta_next = bn;
         h.stepping = true;
     });
@@ -1316,6 +1323,14 @@ pa_status pa_batch_waves_per_block(const pa_batch* b, int32_t run, int32_t* wpb)
             return PA_OK;
         }
     return PA_EINVAL;
+}
+
+pa_status pa_batch_choice_stats(const pa_batch* b, int32_t run, int64_t* alpha_evals, double* host_seconds)
+{
+    if (!b || run < 0 || run >= b->nruns || !alpha_evals || !host_seconds) return PA_EINVAL;
+    *alpha_evals = b->runs[(size_t)run].alpha_evals;
+    *host_seconds = b->runs[(size_t)run].choose_s;
+    return PA_OK;
 }
 
 pa_status pa_batch_learned_stats(const pa_batch* b, int32_t run, int32_t* proposals, int32_t* accepted)

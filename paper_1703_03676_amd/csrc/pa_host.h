@@ -140,12 +140,15 @@ inline double overlap(const Hist& h, int64_t R, int64_t Rprev, double dbeta, std
 
 // Adaptive step (Sec. 2.3): beta_f if alpha(beta_f) >= alpha_star, else the low
 // end of 50 bisection halvings of [beta, beta_f] that keep alpha >= alpha_star.
-// Returns false if no step above beta reaches the target.
+// Returns false if no step above beta reaches the target.  `evals` (may be
+// null) is increased by the number of overlap evaluations made.
 inline bool adapt_beta(const Hist& h, int64_t R, int64_t Rprev, double beta, double beta_f, double alpha_star,
-                       double* beta_next, double* alpha_next, std::vector<double>& w)
+                       double* beta_next, double* alpha_next, std::vector<double>& w, int64_t* evals = nullptr)
 {
+    int64_t n_eval = 1;
     const double a_f = overlap(h, R, Rprev, beta_f - beta, w);
     if (a_f >= alpha_star) {
+        if (evals) *evals += n_eval;
         *beta_next = beta_f;
         if (alpha_next) *alpha_next = a_f;
         return true;
@@ -153,11 +156,13 @@ inline bool adapt_beta(const Hist& h, int64_t R, int64_t Rprev, double beta, dou
     double lo = beta, hi = beta_f;
     for (int it = 0; it < 50; ++it) {
         const double mid = lo + 0.5 * (hi - lo);
+        ++n_eval;
         if (overlap(h, R, Rprev, mid - beta, w) >= alpha_star)
             lo = mid;
         else
             hi = mid;
     }
+    if (evals) *evals += n_eval + (lo != beta && alpha_next ? 1 : 0);
     if (lo == beta) return false;
     *beta_next = lo;
     if (alpha_next) *alpha_next = overlap(h, R, Rprev, lo - beta, w);
