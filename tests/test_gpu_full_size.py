@@ -102,61 +102,86 @@ def test_l64_r20000_first_two_steps_every_replica(layout, oracle_l64_two_steps):
     g.close()
 
 
-def test_l128_r50000_adaptive_first_three_steps():
-    L, R, theta, alpha = 128, 50000, 50, 0.85
-    print("case l128 r50000 adaptive three steps, %d oracle threads" % _threads(), flush=True)
+@pytest.fixture(scope="module")
+def l128_adaptive():
+    """GPU and oracle runs at L = 128, R = 50000 with the multi-histogram
+    record, compared at beta_0; the tests below advance both one adaptive step
+    each (one test per step keeps every test well under a minute or two)."""
+    L, R = 128, 50000
+    print("case l128 r50000 adaptive, %d oracle threads" % _threads(), flush=True)
     g = pa.Run(L, R, seed=3, layout="bits", mhr=True)
     o = oracle.Run(L, R, seed=3)
     o.set_threads(_threads())
     o.init()
     _same_obs(g.observables(), o.measure(), "beta0")
-    got = g.anneal(beta_f=1.0, alpha_star=alpha, theta=theta, mode="adaptive", max_steps=3)
-    assert len(got) == 3
-    for i in range(3):
-        b = o.adapt_beta(alpha, 1.0)
-        assert got[i]["beta"] == b, (i, got[i]["beta"], b)
-        o.resample(b)
-        o.sweep(theta)
-        _same_obs(got[i], o.measure(), "step %d" % (i + 1))
-        print("  step %d beta %.6f equal" % (i + 1, b), flush=True)
-    _same_population(g, o, "after three steps")
-    betas = np.linspace(0.0, got[-1]["beta"] * 1.5, 9)
-    for go, oo in zip(g.reweight(betas), o.reweight(betas)):
-        for k in ("e", "C", "abs_m", "m2", "m4", "betaF_per_N", "S_per_N"):
-            assert _close(go[k], oo[k]), (k, go[k], oo[k])
+    state = {"g": g, "o": o, "done": 0, "betas": [0.0]}
+    yield state
     g.close()
 
 
-@pytest.mark.parametrize("L,R", [(128, 50000), (256, 100000)])
-def test_full_size_init_and_resample_every_replica(L, R):
-    print("case full-size init + resample L=%d R=%d, %d oracle threads" % (L, R, _threads()), flush=True)
+@pytest.mark.parametrize("step", [1, 2, 3])
+def test_l128_r50000_adaptive_step(step, l128_adaptive):
+    theta, alpha = 50, 0.85
+    st = l128_adaptive
+    assert st["done"] == step - 1, "steps run in order"
+    g, o = st["g"], st["o"]
+    print("case l128 r50000 adaptive step %d" % step, flush=True)
+    got = g.anneal(beta_f=1.0, alpha_star=alpha, theta=theta, mode="adaptive", max_steps=1)
+    assert len(got) == 1
+    b = o.adapt_beta(alpha, 1.0)
+    assert got[0]["beta"] == b, (step, got[0]["beta"], b)
+    o.resample(b)
+    o.sweep(theta)
+    _same_obs(got[0], o.measure(), "step %d" % step)
+    st["done"] = step
+    st["betas"].append(b)
+    if step == 3:
+        _same_population(g, o, "after three steps")
+        betas = np.linspace(0.0, b * 1.5, 9)
+        for go, oo in zip(g.reweight(betas), o.reweight(betas)):
+            for k in ("e", "C", "abs_m", "m2", "m4", "betaF_per_N", "S_per_N"):
+                assert _close(go[k], oo[k]), (k, go[k], oo[k])
+
+
+@pytest.fixture(scope="module", params=[(128, 50000), (256, 100000)], ids=["128-50000", "256-100000"])
+def oracle_init_resample(request):
+    """Oracle's initial state and first resampling of a full-size population."""
+    L, R = request.param
+    print("case oracle full-size init + resample L=%d R=%d, %d threads" % (L, R, _threads()), flush=True)
     o = oracle.Run(L, R, seed=4, run_id=2)
     o.set_threads(_threads())
     o.init()
-    oo0 = o.measure()
-    os0, oE0, oM0 = o.get_population()
     # a typical adaptive step at L = 128; at L = 256 a large one, where a few
     # low-energy parents take almost all of the population
     beta = 0.002 if L == 128 else 0.2
-    oi = o.resample(beta)
-    ocounts = o.get_counts()
-    oo1 = o.measure()
-    os1, oE1, oM1 = o.get_population()
+    res = {"L": L, "R": R, "beta": beta, "obs0": o.measure(), "pop0": o.get_population()}
+    res["info"] = o.resample(beta)
+    res["counts"] = o.get_counts()
+    res["obs1"] = o.measure()
+    res["pop1"] = o.get_population()
     del o
-    for layout in ("bits", "int8"):
-        print("  layout %s" % layout, flush=True)
-        g = pa.Run(L, R, seed=4, run_id=2, layout=layout)
-        _same_obs(g.observables(), oo0, "init")
-        gs, gE, gM = g.download_population()
-        assert np.array_equal(gE, oE0) and np.array_equal(gM, oM0)
-        assert np.array_equal(gs, os0)
-        del gs
-        gi = g.resample(beta)
-        assert gi == oi, (gi, oi)
-        assert np.array_equal(g.download_counts(g.capacity), ocounts)
-        _same_obs(g.observables(), oo1, "resample")
-        gs, gE, gM = g.download_population()
-        assert np.array_equal(gE, oE1) and np.array_equal(gM, oM1)
-        assert np.array_equal(gs, os1)
-        del gs
-        g.close()
+    return res
+
+
+@pytest.mark.parametrize("layout", ["bits", "int8"])
+def test_full_size_init_and_resample_every_replica(layout, oracle_init_resample):
+    ref = oracle_init_resample
+    L, R, beta = ref["L"], ref["R"], ref["beta"]
+    print("case full-size init + resample L=%d R=%d layout=%s" % (L, R, layout), flush=True)
+    g = pa.Run(L, R, seed=4, run_id=2, layout=layout)
+    _same_obs(g.observables(), ref["obs0"], "init")
+    gs, gE, gM = g.download_population()
+    os_, oE, oM = ref["pop0"]
+    assert np.array_equal(gE, oE) and np.array_equal(gM, oM)
+    assert np.array_equal(gs, os_)
+    del gs
+    gi = g.resample(beta)
+    assert gi == ref["info"], (gi, ref["info"])
+    assert np.array_equal(g.download_counts(g.capacity), ref["counts"])
+    _same_obs(g.observables(), ref["obs1"], "resample")
+    gs, gE, gM = g.download_population()
+    os_, oE, oM = ref["pop1"]
+    assert np.array_equal(gE, oE) and np.array_equal(gM, oM)
+    assert np.array_equal(gs, os_)
+    del gs
+    g.close()
