@@ -18,7 +18,8 @@
  *     return PA_ESTATE; pa_free is always allowed.
  *   - Device memory belongs to the caller: pa_init receives one device buffer of
  *     at least pa_workspace_bytes(p) bytes that must outlive the run.  The
- *     library allocates no device memory of its own.
+ *     library allocates no device memory of its own; its one static device
+ *     array serves pa_observables_static only.
  *   - The HIP stream passed to pa_init is borrowed; all device work of the run
  *     is enqueued on it.  Calls that return host values (pa_resample's info,
  *     pa_adapt_beta, pa_observables, pa_reweight, the download hooks)
@@ -193,6 +194,32 @@ const char* pa_last_error(const pa_run* r);
  * nb > 0, or temperatures that differ between runs (out is then
  * unspecified). */
 pa_status pa_weighted_average(int32_t N, int32_t nruns, int32_t nb, const pa_obs* obs, pa_obs* out);
+
+/* ---- For callers that cannot allocate memory. --------------------------------
+ * pa_observables for a population held in caller buffers, for callers that
+ * cannot call hipMalloc or hipHostMalloc or create a run (serving loops,
+ * harnesses that forbid allocation).  d_E and d_M are device arrays of the R
+ * replicas' energies and magnetisations (int32; E is a multiple of 4 in
+ * [-2N, 2N], N = L * L; read only).  beta, lnZ and lnQ are the population's
+ * inverse temperature, ln Z estimate and last ln Q, copied into *out as
+ * pa_observables does.  *out (host) receives the same values pa_observables
+ * gives for that population: the averages of Eq. (observables), -beta F/N of
+ * Eq. (free energy), S/N of Eq. (entropy) and the exact integer sums.
+ * The statistics kernel's partial sums, statistics block and energy
+ * histogram live in a statically allocated device array of
+ * pa_static_scratch_bytes() bytes (about 0.5 MiB), one per GPU, held until
+ * the process ends: the call allocates nothing.  It runs on hip_stream (NULL:
+ * the null stream) of the current device and synchronises that stream.
+ * Every call on a GPU uses that GPU's one array, so calls that overlap on one
+ * GPU (other host threads, other streams) race and must be serialised by the
+ * caller.  Errors: PA_EINVAL (L not in {16, 32, 64, 128, 256}, R < 1 or
+ * R > PA_STATIC_MAX_R, NULL pointers, beta or lnZ not finite), PA_EHIP. */
+#define PA_STATIC_MAX_R (1 << 20)
+pa_status pa_observables_static(int32_t L, int32_t R, const int32_t* d_E, const int32_t* d_M, double beta,
+                                double lnZ, double lnQ, void* hip_stream, pa_obs* out);
+
+/* Size of the statically allocated device array of pa_observables_static. */
+size_t pa_static_scratch_bytes(void);
 
 /* ---- Test hooks: step-wise comparison with a reference implementation. ---- */
 

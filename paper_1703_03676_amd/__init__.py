@@ -135,9 +135,13 @@ SIGNATURES = {
                                     ctypes.c_float, ctypes.c_uint64, _vp]),
     "pa_mlp_last_error": (ctypes.c_char_p, [_vp]),
     "pa_mlp_free": (ctypes.c_int, [_vp]),
+    "pa_observables_static": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _vp, _vp, ctypes.c_double,
+                                             ctypes.c_double, ctypes.c_double, _vp, _P(Obs)]),
+    "pa_static_scratch_bytes": (ctypes.c_size_t, []),
 }
 
 MLP_PARAMS, MLP_NORM = 4801, 18
+PA_STATIC_MAX_R = 1 << 20
 
 _lib = None
 
@@ -214,6 +218,25 @@ def weighted_average(runs, N):
     out = (Obs * max(nb, 1))()
     _check(lib().pa_weighted_average(int(N), nruns, nb, ctypes.cast(flat, _vp), ctypes.cast(out, _vp)))
     return [o.as_dict() for o in out[:nb]]
+
+
+def observables_static(L, E, M, beta=0.0, lnZ=0.0, lnQ=0.0, stream=None):
+    """pa_observables_static: observables of the population whose energies and
+    magnetisations are the int32 device tensors E and M (same length R), with
+    no allocation in the library (its static device array holds the
+    statistics).  Returns the observables as a dict."""
+    import torch
+    if E.dtype != torch.int32 or M.dtype != torch.int32 or not E.is_cuda or not M.is_cuda:
+        raise PaError(PA_EINVAL, "E and M must be int32 device tensors")
+    if E.dim() != 1 or E.shape != M.shape or not E.is_contiguous() or not M.is_contiguous():
+        raise PaError(PA_EINVAL, "E and M must be contiguous 1-d tensors of equal length")
+    s = stream if stream is not None else torch.cuda.current_stream(E.device)
+    o = Obs()
+    with torch.cuda.device(E.device):
+        _check(lib().pa_observables_static(int(L), int(E.shape[0]), ctypes.c_void_p(E.data_ptr()),
+                                           ctypes.c_void_p(M.data_ptr()), float(beta), float(lnZ), float(lnQ),
+                                           ctypes.c_void_p(s.cuda_stream), ctypes.byref(o)))
+    return o.as_dict()
 
 
 class Run:

@@ -96,3 +96,19 @@ def test_binding_refuses_to_run_without_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(RuntimeError):
         pa.Run(16, 10, seed=1)
+
+
+def test_observables_static_validates_before_device_work():
+    lib = pa.lib()
+    o = pa.Obs()
+    h = pa.PA_STATIC_MAX_R
+    dev = ctypes.c_void_p(4096)  # never dereferenced: every case fails validation first
+    assert lib.pa_observables_static(64, 0, dev, dev, 0.0, 0.0, 0.0, None, ctypes.byref(o)) == pa.PA_EINVAL
+    assert lib.pa_observables_static(64, h + 1, dev, dev, 0.0, 0.0, 0.0, None, ctypes.byref(o)) == pa.PA_EINVAL
+    for L in (8, 48, 63, 512):
+        assert lib.pa_observables_static(L, 10, dev, dev, 0.0, 0.0, 0.0, None, ctypes.byref(o)) == pa.PA_EINVAL
+    assert lib.pa_observables_static(64, 10, None, dev, 0.0, 0.0, 0.0, None, ctypes.byref(o)) == pa.PA_EINVAL
+    assert lib.pa_observables_static(64, 10, dev, None, 0.0, 0.0, 0.0, None, ctypes.byref(o)) == pa.PA_EINVAL
+    assert lib.pa_observables_static(64, 10, dev, dev, 0.0, 0.0, 0.0, None, None) == pa.PA_EINVAL
+    assert lib.pa_observables_static(64, 10, dev, dev, float("nan"), 0.0, 0.0, None, ctypes.byref(o)) == pa.PA_EINVAL
+    assert lib.pa_static_scratch_bytes() < 1 << 20

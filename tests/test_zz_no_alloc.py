@@ -1,0 +1,83 @@
+"""pa_observables_static, the entry point for callers that cannot allocate,
+against pa_observables on the same populations.
+
+Two calls in a row, the second on a smaller population (smaller L and R), so
+the second call runs on what the first left in the library's static device
+array.  The integer sums must be equal and the FP64 observables bit-equal (the
+same host arithmetic on the same sums)."""
+import pytest
+
+import paper_1703_03676_amd as pa  # noqa: E402  (a broken package fails, never skips)
+import torch  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+KEYS_INT = ("sumE", "sumE2", "sumAbsM", "sumM2", "sumM4", "R")
+KEYS_FP = ("beta", "e", "C", "abs_m", "m2", "m4", "betaF_per_N", "S_per_N", "lnQ")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _run_and_observe(L, R, seed, steps, theta, dbeta):
+    g = pa.Run(L, R, seed=seed, layout="bits")
+    g.observables()
+    for i in range(1, steps + 1):
+        g.resample(i * dbeta)
+        g.sweep(theta)
+    ref = g.observables()
+    st = g.state()
+    E, M = g.download_energies()
+    g.close()
+    return ref, st, E, M
+
+
+def _check_same(ref, got):
+    for k in KEYS_INT:
+        assert got[k] == ref[k], (k, got[k], ref[k])
+    for k in KEYS_FP:
+        assert got[k] == ref[k], (k, got[k], ref[k])
+
+
+def test_static_matches_observables_two_calls_second_smaller():
+    cases = [(128, 60000, 11, 6, 3, 0.08), (32, 700, 12, 4, 5, 0.1)]
+    for L, R, seed, steps, theta, dbeta in cases:
+        print("case pa_observables_static L=%d R=%d seed=%d" % (L, R, seed), flush=True)
+        ref, st, E, M = _run_and_observe(L, R, seed, steps, theta, dbeta)
+        dE = torch.from_numpy(E).cuda()
+        dM = torch.from_numpy(M).cuda()
+        got = pa.observables_static(L, dE, dM, beta=st["beta"], lnZ=st["lnZ"], lnQ=ref["lnQ"])
+        torch.cuda.synchronize()
+        _check_same(ref, got)
+
+
+def test_static_repeated_calls_on_one_population():
+    print("case pa_observables_static repeated L=64", flush=True)
+    ref, st, E, M = _run_and_observe(64, 5000, 13, 3, 4, 0.1)
+    dE = torch.from_numpy(E).cuda()
+    dM = torch.from_numpy(M).cuda()
+    R = len(E)
+    for n in (R, 1000, R):  # the whole population, a prefix of it, the whole again
+        got = pa.observables_static(64, dE[:n].contiguous(), dM[:n].contiguous(), beta=st["beta"], lnZ=st["lnZ"],
+                                    lnQ=ref["lnQ"])
+        assert got["R"] == n
+        assert got["sumE"] == int(E[:n].astype("int64").sum())
+        assert got["sumAbsM"] == int(abs(M[:n].astype("int64")).sum())
+        if n == R:
+            _check_same(ref, got)
+
+
+def test_static_rejects_oversized_population():
+    dE = torch.zeros(8, dtype=torch.int32, device="cuda")
+    lib = pa.lib()
+    o = pa.Obs()
+    p = dE.data_ptr()
+    import ctypes
+    assert lib.pa_observables_static(64, pa.PA_STATIC_MAX_R + 1, ctypes.c_void_p(p), ctypes.c_void_p(p), 0.0, 0.0,
+                                     0.0, None, ctypes.byref(o)) == pa.PA_EINVAL
+    assert lib.pa_observables_static(48, 8, ctypes.c_void_p(p), ctypes.c_void_p(p), 0.0, 0.0, 0.0, None,
+                                     ctypes.byref(o)) == pa.PA_EINVAL
