@@ -91,12 +91,12 @@ def one_run(pa, torch, seed, layout, sweep_events=None):
     return flips, last
 
 
-def anneal_run(pa, seed, layout, sweeps=None, heatbath=False):
+def anneal_run(pa, seed, layout, sweeps=None, heatbath=False, lcg=False):
     """One full run through pa_anneal (the whole schedule in one call, one
     host round trip per temperature step).  The library times every sweep
     launch with HIP events on the run's stream; (ms, flips) pairs are appended
     to `sweeps`."""
-    run = pa.Run(L, R, seed=seed, layout=layout, heatbath=heatbath)
+    run = pa.Run(L, R, seed=seed, layout=layout, heatbath=heatbath, lcg=lcg)
     run.observables()
     obs, ms = run.anneal(beta_f=1.0, dbeta=DBETA, theta=THETA, mode="fixed", sweep_times=True)
     run.close()
@@ -107,16 +107,20 @@ def anneal_run(pa, seed, layout, sweeps=None, heatbath=False):
     return sum(flips), obs[-1]
 
 
-def time_layout(pa, torch, layout, steps, warmup):
-    """Timed full runs through pa_anneal (the headline)."""
+UPDATES = {"metropolis": {}, "heatbath": {"heatbath": True}, "lcg": {"lcg": True}}
+
+
+def time_layout(pa, torch, layout, steps, warmup, update="metropolis"):
+    """Timed full runs through pa_anneal (the headline: Metropolis)."""
+    kw = UPDATES[update]
     for w in range(warmup):
-        anneal_run(pa, 1 + w % 3, layout)
+        anneal_run(pa, 1 + w % 3, layout, **kw)
     torch.cuda.synchronize()
     sweeps = []
     total_flips = 0
     t0 = time.perf_counter()
     for k in range(steps):
-        f, last = anneal_run(pa, 1 + k % 3, layout, sweeps)
+        f, last = anneal_run(pa, 1 + k % 3, layout, sweeps, **kw)
         total_flips += f
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
@@ -292,8 +296,11 @@ def workload_batch64(pa, torch, sequential=True):
     t = time.perf_counter() - t0
     steps = sum(len(b.history(r)) - 1 for r in range(len(runs)))
     flips = sum(sp["L"] ** 2 * theta * o["R"] for r, sp in enumerate(runs) for o in b.history(r)[1:])
+    ev_a = sum(b.choice_stats(r)[0] for r in range(len(runs)))
+    host_a = sum(b.choice_stats(r)[1] for r in range(len(runs)))
     out["batched_adaptive"] = {"s_per_run": t / len(runs), "total_s": t, "flips_per_ns": flips / (t * 1e9),
-                               "steps": steps, "mean_abs_dbetaF_per_N": float(np.mean(_batch_errors(b, runs)))}
+                               "steps": steps, "mean_abs_dbetaF_per_N": float(np.mean(_batch_errors(b, runs))),
+                               "overlap_evals_per_step": ev_a / steps, "host_us_choosing_per_step": 1e6 * host_a / steps}
     # learned: train on the bisection pairs of the adaptive batch, then new seeds
     x, tt = b.training_pairs()
     b.close()
@@ -316,8 +323,11 @@ def workload_batch64(pa, torch, sequential=True):
     acc = sum(bl.learned_stats(r)[1] for r in range(len(runs2)))
     steps = sum(len(bl.history(r)) - 1 for r in range(len(runs2)))
     flips = sum(sp["L"] ** 2 * theta * o["R"] for r, sp in enumerate(runs2) for o in bl.history(r)[1:])
+    ev_l = sum(bl.choice_stats(r)[0] for r in range(len(runs2)))
+    host_l = sum(bl.choice_stats(r)[1] for r in range(len(runs2)))
     out["batched_learned"] = {"s_per_run": t / len(runs2), "total_s": t, "flips_per_ns": flips / (t * 1e9),
                               "steps": steps, "proposals": props, "accepted": acc,
+                              "overlap_evals_per_step": ev_l / steps, "host_us_choosing_per_step": 1e6 * host_l / steps,
                               "mean_abs_dbetaF_per_N": float(np.mean(_batch_errors(bl, runs2))),
                               "training_pairs": int(len(tt)), "train_s": t_train,
                               "train_loss_first_last": [float(losses[0]), float(losses[-1])]}
@@ -383,20 +393,21 @@ def workload_l256_learned(pa, torch):
 
 def workload_l64_heatbath(pa, torch):
     """The headline workload (L=64, R=20000, theta=100, 200 fixed steps of
-    dbeta = 0.005, bit store, through pa_anneal) with heat-bath sweeps, next
-    to the same runs with Metropolis sweeps in the same process: run time,
-    sweep kernel time and the free-energy error at beta = 1 against the exact
-    finite-torus value, over three seeds each."""
+    dbeta = 0.005, bit store, through pa_anneal) with each update rule in the
+    same process: Metropolis with the bit-sliced Philox uniforms, heat-bath,
+    and Metropolis with the in-line LCG uniforms of the paper's multi-spin
+    variant.  Run time, sweep kernel time and the free-energy error at
+    beta = 1 against the exact finite-torus value, over three seeds each."""
     exact_bf = _exact_betaF(L, 1.0)
     out = {"workload": "L=64, R=20000, theta=100, beta 0->1 in 200 steps of 0.005, bit store, pa_anneal: "
-                       "heat-bath vs Metropolis sweeps"}
-    for name, hb in (("metropolis", False), ("heatbath", True)):
-        anneal_run(pa, 9, "bits", heatbath=hb)  # warm-up
+                       "Metropolis vs heat-bath vs LCG-variant sweeps"}
+    for name, hb, lcg in (("metropolis", False, False), ("heatbath", True, False), ("lcg", False, True)):
+        anneal_run(pa, 9, "bits", heatbath=hb, lcg=lcg)  # warm-up
         torch.cuda.synchronize()
         sweeps, errs, flips = [], [], 0
         t0 = time.perf_counter()
         for seed in (1, 2, 3):
-            f, last = anneal_run(pa, seed, "bits", sweeps, heatbath=hb)
+            f, last = anneal_run(pa, seed, "bits", sweeps, heatbath=hb, lcg=lcg)
             flips += f
             errs.append(abs(last["betaF_per_N"] - exact_bf))
         torch.cuda.synchronize()
@@ -517,8 +528,11 @@ def main():
     ap.add_argument("--calibration-copy", action="store_true",
                     help="end with one pa_resample of a fresh L=64, R=20000 population, whose replica copy "
                          "(known bytes) calibrates the HBM counters of a profiling run")
+    ap.add_argument("--update", default="metropolis", choices=sorted(UPDATES),
+                    help="update rule of the l64 workload's sweeps (the headline is metropolis)")
     ap.add_argument("--workload", default="l64",
                     choices=["l64", "l128_adaptive", "batch64", "l256_learned", "resample_l256", "l64_heatbath",
+                             "l64_update_rules",
                              "paper_tables", "sweeps"],
                     help="l64 (default) is the headline workload; the others print their own JSON line")
     args = ap.parse_args()
@@ -537,14 +551,15 @@ def main():
     if args.workload != "l64":
         fn = {"l128_adaptive": workload_l128_adaptive, "batch64": workload_batch64,
               "l256_learned": workload_l256_learned, "resample_l256": workload_resample_l256,
-              "l64_heatbath": workload_l64_heatbath, "paper_tables": workload_paper_tables,
+              "l64_heatbath": workload_l64_heatbath, "l64_update_rules": workload_l64_heatbath,
+              "paper_tables": workload_paper_tables,
               "sweeps": workload_sweeps}[args.workload]
         res = fn(pa, torch)
         res.pop("_model", None)
         print(json.dumps(res), flush=True)
         return 0
     layouts = args.layouts.split(",")
-    res = {lay: time_layout(pa, torch, lay, args.steps, args.warmup) for lay in layouts}
+    res = {lay: time_layout(pa, torch, lay, args.steps, args.warmup, args.update) for lay in layouts}
     steps_cmp = None if args.no_step_calls else time_step_calls(pa, torch, layouts[0], 2)
     if args.calibration_copy:
         cal = pa.Run(L, R, seed=9, layout=layouts[0])
@@ -554,7 +569,7 @@ def main():
         cal.close()
     head = res[layouts[0]]
     achieved = head["sweep_flips_avg"] * SLOTS_PER_FLIP / (head["sweep_ms_avg"] * 1e-3)
-    traffic = measured_traffic()
+    traffic = measured_traffic() if args.update == "metropolis" else None
     # algorithmic HBM bytes of one sweep launch: every replica's spins read and
     # written once for all theta sweeps (N/8 or N bytes each way) plus E and M
     rep_bytes = L * L // 8 if layouts[0] == "bits" else L * L
@@ -579,6 +594,7 @@ def main():
                         "spin store: %s; one step = one full PA run (pa_anneal)" % layouts[0],
             "L": L, "R": R, "theta": THETA, "dbeta": DBETA, "temperature_steps": NSTEPS,
             "layout": layouts[0],
+            "update": args.update,
         },
         "run_wall_time_s": round(head["ms_per_run"] / 1e3, 4),
         "roofline": {
