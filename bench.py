@@ -599,7 +599,8 @@ def main():
         "run_wall_time_s": round(head["ms_per_run"] / 1e3, 4),
         "roofline": {
             "bound": "alu",
-            "kernel": "sweep_kernel<64,bits>",
+            "kernel": ("rp_sweep_kernel<64>" if layouts[0] == "interleaved"
+                       else "sweep_kernel<64,%s>" % layouts[0]),
             "achieved": round(achieved / 1e12, 3),
             "peak": round(VALU_PEAK_SLOTS / 1e12, 2),
             "unit": "Tops/s (VALU lane-slots, %.1f per attempted flip)" % SLOTS_PER_FLIP,

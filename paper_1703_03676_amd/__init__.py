@@ -17,11 +17,11 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libpa.so")
 
 PA_OK, PA_EINVAL, PA_ENOMEM, PA_ECAPACITY, PA_EHIP, PA_ESTATE, PA_EEXTINCT = 0, -1, -2, -3, -4, -5, -6
-PA_SPIN_INT8, PA_SPIN_BITS = 0, 1
+PA_SPIN_INT8, PA_SPIN_BITS, PA_SPIN_INTERLEAVED = 0, 1, 2
 PA_FLAG_MHR = 1
 PA_FLAG_HEATBATH = 2
 PA_FLAG_LCG = 4
-LAYOUTS = {"int8": PA_SPIN_INT8, "bits": PA_SPIN_BITS}
+LAYOUTS = {"int8": PA_SPIN_INT8, "bits": PA_SPIN_BITS, "interleaved": PA_SPIN_INTERLEAVED}
 SUPPORTED_L = (16, 32, 64, 128, 256)
 
 

@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpa.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("pa_api.hip", "pa_sweep.hip", "pa_kernels.hip", "pa_batch.hip", "pa_mlp.hip", "pa_static.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("pa_api.hip", "pa_sweep.hip", "pa_kernels.hip", "pa_batch.hip", "pa_mlp.hip", "pa_static.hip", "pa_rp.hip")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -39,7 +39,8 @@ int32_t default_capacity(int32_t R)
 
 struct Layout {
     size_t spin[2], E[2], M[2], counts, parent, bsum, tbl, stats, parts, mhr, total;
-    size_t rep_bytes;
+    size_t rep_bytes;   // bytes of one replica
+    uint32_t stride;    // interleaved store: bytes per site row (capacity rounded up to 64); else 0
     int32_t capacity, nbins, nblk;
 };
 
@@ -47,7 +48,7 @@ struct Layout {
 bool make_layout(const pa_params* p, Layout* lo)
 {
     if (!p || !lattice_supported(p->L) || p->R < 1) return false;
-    if (p->layout != PA_SPIN_INT8 && p->layout != PA_SPIN_BITS) return false;
+    if (p->layout != PA_SPIN_INT8 && p->layout != PA_SPIN_BITS && p->layout != PA_SPIN_INTERLEAVED) return false;
     if (p->flags & ~(uint32_t)(PA_FLAG_MHR | PA_FLAG_HEATBATH | PA_FLAG_LCG)) return false;
     if ((p->flags & PA_FLAG_HEATBATH) && (p->flags & PA_FLAG_LCG)) return false;
     if (p->run_id >= (1u << 28)) return false;
@@ -56,7 +57,8 @@ bool make_layout(const pa_params* p, Layout* lo)
     const int64_t N = (int64_t)p->L * p->L;
     lo->capacity = (int32_t)cap;
     lo->nbins = (int32_t)N + 1;
-    lo->rep_bytes = (p->layout == PA_SPIN_INT8) ? (size_t)N : (size_t)N / 8;
+    lo->rep_bytes = (p->layout == PA_SPIN_BITS) ? (size_t)N / 8 : (size_t)N;
+    lo->stride = (p->layout == PA_SPIN_INTERLEAVED) ? (uint32_t)((cap + 63) / 64 * 64) : 0u;
     lo->nblk = (int32_t)((cap + pa::kBlock - 1) / pa::kBlock);
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -65,7 +67,7 @@ bool make_layout(const pa_params* p, Layout* lo)
         return at;
     };
     for (int b = 0; b < 2; ++b) {
-        lo->spin[b] = take((size_t)cap * lo->rep_bytes);
+        lo->spin[b] = take(lo->stride ? (size_t)N * lo->stride : (size_t)cap * lo->rep_bytes);
         lo->E[b] = take((size_t)cap * 4);
         lo->M[b] = take((size_t)cap * 4);
     }
@@ -166,6 +168,17 @@ void key_of(const pa_run* r, uint32_t* k0, uint32_t* k1, uint32_t* tag)
     *tag = r->p.run_id << 4;
 }
 
+// The sweep kernel of the run's spin store: bit-sliced (int8 and bit stores)
+// or replica-parallel (interleaved store).
+hipError_t launch_sweep_of(const pa_run* r, pa::SweepArgs& a)
+{
+    if (r->p.layout == PA_SPIN_INTERLEAVED) {
+        a.stride = r->lo.stride;
+        return pa::launch_sweep_rp(r->L, update_of(r->p), a, r->stream);
+    }
+    return pa::launch_sweep(r->L, r->p.layout, update_of(r->p), a, r->stream);
+}
+
 pa_status launch_sweeps(pa_run* r, int32_t nsweeps, bool init)
 {
     pa::SweepArgs a;
@@ -181,7 +194,7 @@ pa_status launch_sweeps(pa_run* r, int32_t nsweeps, bool init)
     host::sweep_thresholds(hb, r->beta, &a.t2h, &a.t2l, &a.t4h, &a.t4l);
     a.init = init ? 1 : 0;
     a.qcap = r->qcap;
-    HIPCHK(pa::launch_sweep(r->L, r->p.layout, update_of(r->p), a, r->stream));
+    HIPCHK(launch_sweep_of(r, a));
     return PA_OK;
 }
 
@@ -247,7 +260,11 @@ pa_status queue_resample(pa_run* r, double beta_next, bool copy, double* lnQ, in
                              sc.counts, sc.bsum, r->stream));
     HIPCHK(pa::launch_scatter(sc.counts, sc.bsum, n, r->lo.capacity, sc.parent, r->stats, r->hist, r->nbins,
                               r->stream));
-    if (copy)
+    if (copy && r->p.layout == PA_SPIN_INTERLEAVED)
+        HIPCHK(pa::launch_copy_rp(r->spin[r->cur], r->E[r->cur], r->M[r->cur], sc.parent, &r->stats->r_new,
+                                  r->lo.capacity, r->N, r->lo.stride, r->spin[nxt], r->E[nxt], r->M[nxt],
+                                  r->stream));
+    else if (copy)
         HIPCHK(pa::launch_copy(r->spin[r->cur], r->E[r->cur], r->M[r->cur], sc.parent, &r->stats->r_new,
                                r->lo.capacity, r->lo.rep_bytes, r->spin[nxt], r->E[nxt], r->M[nxt], r->stream));
     r->counts_n = n;
@@ -472,8 +489,11 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
         double lnQ;
         int32_t Emin;
         // with sweeps, the sweep kernel loads every child from its parent: the
-        // replica copy and the sweep's load are one pass over the store
-        st = queue_resample(r, bn, sc->theta == 0, &lnQ, &Emin, run_scratch(r));
+        // replica copy and the sweep's load are one pass over the store (the
+        // replica-parallel sweep of the interleaved store works in place and
+        // takes the copy first)
+        const bool gather = sc->theta > 0 && r->p.layout != PA_SPIN_INTERLEAVED;
+        st = queue_resample(r, bn, !gather, &lnQ, &Emin, run_scratch(r));
         if (st != PA_OK) return st;
         const int nxt = r->cur ^ 1;
         const uint32_t* n_dev = &r->stats->r_new;
@@ -485,8 +505,8 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
             a.M = r->M[nxt];
             a.n_rep = r->lo.capacity;
             a.n_dev = n_dev;
-            a.src = r->spin[r->cur];
-            a.parent = r->parent;
+            a.src = gather ? r->spin[r->cur] : nullptr;
+            a.parent = gather ? r->parent : nullptr;
             a.nsweeps = sc->theta;
             a.g0 = (uint32_t)r->sweeps;
             a.key0 = k0;
@@ -497,7 +517,7 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
             host::sweep_thresholds(hb, bn, &a.t2h, &a.t2l, &a.t4h, &a.t4l);
             const bool timed = sweep_ms && done < cap;
             if (timed) HIPCHK(hipEventRecord(r->ev_t0, r->stream));
-            HIPCHK(pa::launch_sweep(r->L, r->p.layout, update_of(r->p), a, r->stream));
+            HIPCHK(launch_sweep_of(r, a));
             if (timed) HIPCHK(hipEventRecord(r->ev_t1, r->stream));
         }
         // (the scatter of queue_resample has cleared the statistics)
@@ -650,6 +670,13 @@ pa_status pa_download_population(pa_run* r, int8_t* spins, int32_t* E, int32_t* 
     if (spins) {
         if (r->p.layout == PA_SPIN_INT8) {
             HIPCHK(hipMemcpyAsync(spins, r->spin[r->cur], n * (size_t)r->N, hipMemcpyDeviceToHost, r->stream));
+        } else if (r->p.layout == PA_SPIN_INTERLEAVED) {
+            // site rows of the first n replicas, then [site][replica] -> [replica][site]
+            std::vector<int8_t> rows(n * (size_t)r->N);
+            HIPCHK(hipMemcpy2DAsync(rows.data(), n, r->spin[r->cur], r->lo.stride, n, (size_t)r->N,
+                                    hipMemcpyDeviceToHost, r->stream));
+            HIPCHK(hipStreamSynchronize(r->stream));
+            host::interleaved_to_int8(rows.data(), (size_t)r->N, n, spins);
         } else {
             std::vector<uint32_t> words(n * (size_t)r->N / 32);
             HIPCHK(hipMemcpyAsync(words.data(), r->spin[r->cur], words.size() * 4, hipMemcpyDeviceToHost, r->stream));
@@ -673,13 +700,17 @@ pa_status pa_download_replicas(pa_run* r, const int32_t* idx, int32_t n, int8_t*
     std::vector<int32_t> e((size_t)n), m((size_t)n);
     for (int32_t k = 0; k < n; ++k) {
         const size_t j = (size_t)idx[k];
-        HIPCHK(hipMemcpyAsync(raw.data() + (size_t)k * rb, r->spin[r->cur] + j * rb, rb, hipMemcpyDeviceToHost,
-                              r->stream));
+        if (r->p.layout == PA_SPIN_INTERLEAVED)  // byte j of every site row
+            HIPCHK(hipMemcpy2DAsync(raw.data() + (size_t)k * rb, 1, r->spin[r->cur] + j, r->lo.stride, 1,
+                                    (size_t)r->N, hipMemcpyDeviceToHost, r->stream));
+        else
+            HIPCHK(hipMemcpyAsync(raw.data() + (size_t)k * rb, r->spin[r->cur] + j * rb, rb, hipMemcpyDeviceToHost,
+                                  r->stream));
         HIPCHK(hipMemcpyAsync(&e[(size_t)k], r->E[r->cur] + j, 4, hipMemcpyDeviceToHost, r->stream));
         HIPCHK(hipMemcpyAsync(&m[(size_t)k], r->M[r->cur] + j, 4, hipMemcpyDeviceToHost, r->stream));
     }
     HIPCHK(hipStreamSynchronize(r->stream));
-    if (r->p.layout == PA_SPIN_INT8)
+    if (r->p.layout != PA_SPIN_BITS)
         std::memcpy(spins, raw.data(), raw.size());
     else
         host::bits_to_int8(reinterpret_cast<const uint32_t*>(raw.data()), r->L, (size_t)n, spins);
@@ -701,6 +732,12 @@ pa_status pa_upload_population(pa_run* r, int32_t R_cur, const int8_t* spins, in
         if (spins[i] != 1 && spins[i] != -1) return PA_EINVAL;
     if (r->p.layout == PA_SPIN_INT8) {
         HIPCHK(hipMemcpyAsync(r->spin[r->cur], spins, n * N, hipMemcpyHostToDevice, r->stream));
+        HIPCHK(hipStreamSynchronize(r->stream));
+    } else if (r->p.layout == PA_SPIN_INTERLEAVED) {
+        std::vector<int8_t> rows(n * N);
+        host::int8_to_interleaved(spins, N, n, rows.data());
+        HIPCHK(hipMemcpy2DAsync(r->spin[r->cur], r->lo.stride, rows.data(), n, n, N, hipMemcpyHostToDevice,
+                                r->stream));
         HIPCHK(hipStreamSynchronize(r->stream));
     } else {
         std::vector<uint32_t> words(n * N / 32, 0u);

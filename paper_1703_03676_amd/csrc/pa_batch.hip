@@ -256,6 +256,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_min_w
     a.key1 = rd.key1;
     a.tag = rd.tag;
     a.qcap = rd.qcap;
+    a.stride = 0u;
     a.t2h = st.t2h;
     a.t2l = st.t2l;
     a.t4h = st.t4h;

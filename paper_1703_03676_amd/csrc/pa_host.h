@@ -328,6 +328,20 @@ inline void bits_to_int8(const uint32_t* words, int L, size_t n, int8_t* spins)
     }
 }
 
+// Site rows of the interleaved store ([site][replica], n replicas per row as
+// copied out of the store) <-> int8 row-major replicas ([replica][site]).
+inline void interleaved_to_int8(const int8_t* rows, size_t N, size_t n, int8_t* spins)
+{
+    for (size_t s = 0; s < N; ++s)
+        for (size_t j = 0; j < n; ++j) spins[j * N + s] = rows[s * n + j];
+}
+
+inline void int8_to_interleaved(const int8_t* spins, size_t N, size_t n, int8_t* rows)
+{
+    for (size_t s = 0; s < N; ++s)
+        for (size_t j = 0; j < n; ++j) rows[s * n + j] = spins[j * N + s];
+}
+
 inline void int8_to_bits(const int8_t* spins, int L, size_t n, uint32_t* words)
 {
     const int N = L * L, half = N / 2, hw = L / 2, wpc = half / 32;

@@ -51,6 +51,8 @@ struct SweepArgs {
     const uint32_t* n_dev;  // if set: the population size is min(*n_dev, n_rep), read on the device
     const uint8_t* src;     // with parent: replica j starts from replica parent[j] of this store
     const uint32_t* parent; // (the resampling copy fused into the sweep's load); else NULL
+    uint32_t stride;        // interleaved store: bytes from one site's row of spins (one byte per
+                            // replica) to the next, the capacity rounded up to 64; 0 for the other stores
 };
 
 constexpr int kBlock = 256;     // threads per block of the population kernels

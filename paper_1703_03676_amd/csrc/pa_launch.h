@@ -37,6 +37,12 @@ hipError_t launch_copy(const uint8_t* src, const int32_t* Esrc, const int32_t* M
                        const uint32_t* n_new, int32_t cap, size_t rep_bytes, uint8_t* dst, int32_t* Edst,
                        int32_t* Mdst, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t value, size_t n, hipStream_t s);
+// Interleaved store (pa_rp.hip): the replica-parallel sweep (a.stride set, no
+// fused gather), and the replica copy of resampling for that store.
+hipError_t launch_sweep_rp(int L, int update, const SweepArgs& a, hipStream_t s);
+hipError_t launch_copy_rp(const uint8_t* src, const int32_t* Esrc, const int32_t* Msrc, const uint32_t* parent,
+                          const uint32_t* n_new, int32_t cap, int32_t N, uint32_t stride, uint8_t* dst, int32_t* Edst,
+                          int32_t* Mdst, hipStream_t s);
 // Clears the range, the sums and the histogram (not r_new).
 hipError_t launch_stats_reset(DevStats* st, uint32_t* hist, int32_t nbins, hipStream_t s);
 

@@ -52,6 +52,9 @@ def test_workspace_bytes_validation():
     assert pa.workspace_bytes(bad_run) == 0
     assert pa.workspace_bytes(pa.make_params(16, 10, 1, run_id=(1 << 28) - 1)) > 0
     assert pa.workspace_bytes(pa.make_params(64, 20000, 1, lcg=True)) == n_bits
+    # interleaved store: N site rows of the capacity rounded up to 64 bytes, twice
+    n_il = pa.workspace_bytes(pa.make_params(64, 20000, 1, layout="interleaved"))
+    assert n_il >= 2 * 4096 * 21504 and n_il >= n_int8
     # the heat-bath update needs no extra device memory
     assert pa.workspace_bytes(pa.make_params(64, 20000, 1, heatbath=True)) == n_bits
     assert pa.workspace_bytes(pa.make_params(64, 20000, 1, heatbath=True, mhr=True)) == \
