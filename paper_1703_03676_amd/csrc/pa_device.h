@@ -106,6 +106,77 @@ __device__ __forceinline__ U4 philox10u(uint32_t c0, uint32_t c1, uint32_t c2, u
     return {c0, c1, c2, c3};
 }
 
+// The register-path sweep evaluates Philox4x32-10 on counters (c0, c1, c2, c3)
+// whose words c1 (sweep and colour), c2 (replica) and c3 (stream) are the same
+// for every block of a half sweep, and the same on every lane of a wave that
+// holds one replica.  The first round's new word 0, hi(M1 c2) ^ c1 ^ k0, then
+// depends on none of c0, and so does the second round's product of it: both
+// are taken once per half sweep (PhiloxHalf) instead of per block, with plain
+// operations that stay scalar when their inputs are.  philox10_h is philox10
+// with those values supplied; the arithmetic is the same.
+struct PhiloxHalf {
+    uint32_t a0;      // round 1: hi(M1 c2) ^ c1 ^ k0
+    uint32_t a1;      // round 1: lo(M1 c2)
+    uint32_t p0h, p0l;  // round 2: the product M0 a0
+};
+
+__device__ __forceinline__ PhiloxHalf philox_half(uint32_t c1, uint32_t c2, uint32_t k0)
+{
+    const uint64_t P1 = (uint64_t)kM1 * c2;
+    PhiloxHalf h;
+    h.a0 = ((uint32_t)(P1 >> 32) ^ c1) ^ k0;
+    h.a1 = (uint32_t)P1;
+    const uint64_t P0 = (uint64_t)kM0 * h.a0;
+    h.p0h = (uint32_t)(P0 >> 32);
+    h.p0l = (uint32_t)P0;
+    return h;
+}
+
+__device__ __forceinline__ U4 philox10_h(uint32_t c0, uint32_t c3, const PhiloxHalf& h, uint32_t k0, uint32_t k1)
+{
+    // round 1 (word 0 and word 1 of its output are h.a0, h.a1)
+    const uint64_t P0 = (uint64_t)kM0 * c0;
+    const uint32_t a2 = (uint32_t)(P0 >> 32) ^ (c3 ^ k1);
+    const uint32_t a3 = (uint32_t)P0;
+    k0 += kW0;
+    k1 += kW1;
+    // round 2 (its product M0 a0 is h.p0h, h.p0l)
+    const uint64_t P1 = (uint64_t)kM1 * a2;
+    uint32_t x0 = (uint32_t)(P1 >> 32) ^ (h.a1 ^ k0);
+    uint32_t x1 = (uint32_t)P1;
+    uint32_t x2 = a3 ^ (h.p0h ^ k1);
+    uint32_t x3 = h.p0l;
+    k0 += kW0;
+    k1 += kW1;
+    // round 3 (word 3 of its input is h.p0l)
+    {
+        const uint64_t p0 = (uint64_t)kM0 * x0;
+        const uint64_t p1 = (uint64_t)kM1 * x2;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), x1, k0);
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ (x3 ^ k1);
+        x1 = (uint32_t)p1;
+        x3 = (uint32_t)p0;
+        x0 = n0;
+        x2 = n2;
+        k0 += kW0;
+        k1 += kW1;
+    }
+#pragma unroll
+    for (int r = 3; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)kM0 * x0;
+        const uint64_t p1 = (uint64_t)kM1 * x2;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), x1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), x3, k1);
+        x1 = (uint32_t)p1;
+        x3 = (uint32_t)p0;
+        x0 = n0;
+        x2 = n2;
+        k0 += kW0;
+        k1 += kW1;
+    }
+    return {x0, x1, x2, x3};
+}
+
 __device__ __forceinline__ uint32_t pick(const U4& v, uint32_t i)
 {
     return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
@@ -270,7 +341,7 @@ __device__ __forceinline__ void compare_plane(uint32_t x, uint32_t tb, uint32_t 
 // of its four neighbours are anti-aligned (k = s h <= 0), else if its uniform
 // x (high 16 bits from the bit planes, low 16 bits drawn on a tie) is below
 // the threshold of its class (one anti-aligned neighbour: k = 2; none: k = 4).
-__device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_t v, uint32_t ctr1, uint32_t j,
+__device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_t v, const PhiloxHalf& ph,
                                                 const SweepArgs& a)
 {
     const uint32_t d1 = w ^ n.up, d2 = w ^ n.dn, d3 = w ^ n.same, d4 = w ^ n.side;
@@ -294,9 +365,9 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_
         // blocks 0, 1 and 2 are computed together (three independent chains),
         // since the first eight planes leave some site of the wave tied almost
         // surely (the wave holds about 2000 sites that need a uniform)
-        const U4 P0 = philox10(4u * v, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
-        const U4 P1 = philox10(4u * v + 1u, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
-        const U4 P2 = philox10(4u * v + 2u, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
+        const U4 P0 = philox10_h(4u * v, a.tag | kStreamSweepHigh, ph, a.key0, a.key1);
+        const U4 P1 = philox10_h(4u * v + 1u, a.tag | kStreamSweepHigh, ph, a.key0, a.key1);
+        const U4 P2 = philox10_h(4u * v + 2u, a.tag | kStreamSweepHigh, ph, a.key0, a.key1);
         const uint32_t pl[12] = {P0.x, P0.y, P0.z, P0.w, P1.x, P1.y, P1.z, P1.w, P2.x, P2.y, P2.z, P2.w};
 #pragma unroll
         for (int q = 0; q < 12; ++q) {
@@ -307,7 +378,7 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_
 #pragma unroll
         for (int kk = 3; kk < 4; ++kk) {
             if (!__any(eq != 0u)) break;
-            const U4 P = philox10(4u * v + (uint32_t)kk, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
+            const U4 P = philox10_h(4u * v + (uint32_t)kk, a.tag | kStreamSweepHigh, ph, a.key0, a.key1);
             const uint32_t pq[4] = {P.x, P.y, P.z, P.w};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -323,7 +394,7 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_
             const int b = __builtin_ctz(tie);
             tie &= tie - 1u;
             const uint32_t q = 32u * v + (uint32_t)b;
-            const U4 P = philox10(q >> 3, ctr1, j, a.tag | kStreamSweepLow, a.key0, a.key1);
+            const U4 P = philox10_h(q >> 3, a.tag | kStreamSweepLow, ph, a.key0, a.key1);
             const uint32_t word = pick(P, (q >> 1) & 3u);
             const uint32_t lo = (q & 1u) ? (word & 0xFFFFu) : (word >> 16);
             const uint32_t tl = ((cls1 >> b) & 1u) ? a.t2l : a.t4l;
@@ -363,15 +434,15 @@ __device__ __forceinline__ HbClass hb_classes(uint32_t w, const Nb& n)
 // so those sites compare the complement of their uniform with U_|k| (the
 // planes and the low half xored with neg) and take the opposite result.  The
 // k = 0 sites are decided by the top bit of x alone.
-__device__ __forceinline__ uint32_t heatbath_mask(uint32_t w, const Nb& n, uint32_t v, uint32_t ctr1, uint32_t j,
+__device__ __forceinline__ uint32_t heatbath_mask(uint32_t w, const Nb& n, uint32_t v, const PhiloxHalf& ph,
                                                   const SweepArgs& a)
 {
     const HbClass c = hb_classes(w, n);
     uint32_t eq = ~c.zero;
     // blocks 0, 1 and 2 together (three independent chains), as in accept_mask
-    const U4 P0 = philox10(4u * v, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
-    const U4 P1 = philox10(4u * v + 1u, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
-    const U4 P2 = philox10(4u * v + 2u, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
+    const U4 P0 = philox10_h(4u * v, a.tag | kStreamSweepHigh, ph, a.key0, a.key1);
+    const U4 P1 = philox10_h(4u * v + 1u, a.tag | kStreamSweepHigh, ph, a.key0, a.key1);
+    const U4 P2 = philox10_h(4u * v + 2u, a.tag | kStreamSweepHigh, ph, a.key0, a.key1);
     const uint32_t pl[12] = {P0.x, P0.y, P0.z, P0.w, P1.x, P1.y, P1.z, P1.w, P2.x, P2.y, P2.z, P2.w};
     uint32_t acc = c.zero & ~pl[0];  // U_0 = 2^31: x < U_0 iff its top bit is 0
 #pragma unroll
@@ -383,7 +454,7 @@ __device__ __forceinline__ uint32_t heatbath_mask(uint32_t w, const Nb& n, uint3
 #pragma unroll
     for (int kk = 3; kk < 4; ++kk) {
         if (!__any(eq != 0u)) break;
-        const U4 P = philox10(4u * v + (uint32_t)kk, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
+        const U4 P = philox10_h(4u * v + (uint32_t)kk, a.tag | kStreamSweepHigh, ph, a.key0, a.key1);
         const uint32_t pq[4] = {P.x, P.y, P.z, P.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -398,7 +469,7 @@ __device__ __forceinline__ uint32_t heatbath_mask(uint32_t w, const Nb& n, uint3
             const int b = __builtin_ctz(tie);
             tie &= tie - 1u;
             const uint32_t q = 32u * v + (uint32_t)b;
-            const U4 P = philox10(q >> 3, ctr1, j, a.tag | kStreamSweepLow, a.key0, a.key1);
+            const U4 P = philox10_h(q >> 3, a.tag | kStreamSweepLow, ph, a.key0, a.key1);
             const uint32_t word = pick(P, (q >> 1) & 3u);
             uint32_t lo = (q & 1u) ? (word & 0xFFFFu) : (word >> 16);
             if ((c.neg >> b) & 1u) lo ^= 0xFFFFu;
@@ -482,14 +553,14 @@ __device__ __forceinline__ void half_sweep(uint32_t (&own)[Geo<L>::K], const uin
 {
     using Gm = Geo<L>;
     const Neighbours<L, C> nb(oth, lane, gl);
-    const uint32_t ctr1 = 2u * g + (uint32_t)C;
+    const PhiloxHalf ph = philox_half(2u * g + (uint32_t)C, j, a.key0);
 #pragma unroll
     for (int k = 0; k < Gm::K; ++k) {
         const uint32_t v = (uint32_t)(gl * Gm::K + k);
         if constexpr (HB)
-            own[k] ^= heatbath_mask(own[k], nb.get(oth, k), v, ctr1, j, a);
+            own[k] ^= heatbath_mask(own[k], nb.get(oth, k), v, ph, a);
         else
-            own[k] ^= accept_mask(own[k], nb.get(oth, k), v, ctr1, j, a);
+            own[k] ^= accept_mask(own[k], nb.get(oth, k), v, ph, a);
     }
 }
 
