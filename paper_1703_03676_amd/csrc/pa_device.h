@@ -177,6 +177,25 @@ __device__ __forceinline__ U4 philox10_h(uint32_t c0, uint32_t c3, const PhiloxH
     return {x0, x1, x2, x3};
 }
 
+// Philox blocks of one half sweep on the register path, counter (c0, 2g + c, j,
+// c3): with one replica per wave (Half) the per-half-sweep values of
+// philox_half are shared by every block, with several (replicas differ
+// between lanes) each block is plain philox10, which measured a few
+// instructions cheaper there.
+struct HalfBlocks {
+    PhiloxHalf h;
+    uint32_t k0, k1;
+    __device__ __forceinline__ U4 operator()(uint32_t c0, uint32_t c3) const { return philox10_h(c0, c3, h, k0, k1); }
+};
+
+struct PlainBlocks {
+    uint32_t c1, c2, k0, k1;
+    __device__ __forceinline__ U4 operator()(uint32_t c0, uint32_t c3) const
+    {
+        return philox10(c0, c1, c2, c3, k0, k1);
+    }
+};
+
 __device__ __forceinline__ uint32_t pick(const U4& v, uint32_t i)
 {
     return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
@@ -341,7 +360,8 @@ __device__ __forceinline__ void compare_plane(uint32_t x, uint32_t tb, uint32_t 
 // of its four neighbours are anti-aligned (k = s h <= 0), else if its uniform
 // x (high 16 bits from the bit planes, low 16 bits drawn on a tie) is below
 // the threshold of its class (one anti-aligned neighbour: k = 2; none: k = 4).
-__device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_t v, const PhiloxHalf& ph,
+template <class BLK>
+__device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_t v, const BLK& blk,
                                                 const SweepArgs& a)
 {
     const uint32_t d1 = w ^ n.up, d2 = w ^ n.dn, d3 = w ^ n.same, d4 = w ^ n.side;
@@ -365,9 +385,9 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_
         // blocks 0, 1 and 2 are computed together (three independent chains),
         // since the first eight planes leave some site of the wave tied almost
         // surely (the wave holds about 2000 sites that need a uniform)
-        const U4 P0 = philox10_h(4u * v, a.tag | kStreamSweepHigh, ph, a.key0, a.key1);
-        const U4 P1 = philox10_h(4u * v + 1u, a.tag | kStreamSweepHigh, ph, a.key0, a.key1);
-        const U4 P2 = philox10_h(4u * v + 2u, a.tag | kStreamSweepHigh, ph, a.key0, a.key1);
+        const U4 P0 = blk(4u * v, a.tag | kStreamSweepHigh);
+        const U4 P1 = blk(4u * v + 1u, a.tag | kStreamSweepHigh);
+        const U4 P2 = blk(4u * v + 2u, a.tag | kStreamSweepHigh);
         const uint32_t pl[12] = {P0.x, P0.y, P0.z, P0.w, P1.x, P1.y, P1.z, P1.w, P2.x, P2.y, P2.z, P2.w};
 #pragma unroll
         for (int q = 0; q < 12; ++q) {
@@ -378,7 +398,7 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_
 #pragma unroll
         for (int kk = 3; kk < 4; ++kk) {
             if (!__any(eq != 0u)) break;
-            const U4 P = philox10_h(4u * v + (uint32_t)kk, a.tag | kStreamSweepHigh, ph, a.key0, a.key1);
+            const U4 P = blk(4u * v + (uint32_t)kk, a.tag | kStreamSweepHigh);
             const uint32_t pq[4] = {P.x, P.y, P.z, P.w};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -394,7 +414,7 @@ __device__ __forceinline__ uint32_t accept_mask(uint32_t w, const Nb& n, uint32_
             const int b = __builtin_ctz(tie);
             tie &= tie - 1u;
             const uint32_t q = 32u * v + (uint32_t)b;
-            const U4 P = philox10_h(q >> 3, a.tag | kStreamSweepLow, ph, a.key0, a.key1);
+            const U4 P = blk(q >> 3, a.tag | kStreamSweepLow);
             const uint32_t word = pick(P, (q >> 1) & 3u);
             const uint32_t lo = (q & 1u) ? (word & 0xFFFFu) : (word >> 16);
             const uint32_t tl = ((cls1 >> b) & 1u) ? a.t2l : a.t4l;
@@ -434,15 +454,16 @@ __device__ __forceinline__ HbClass hb_classes(uint32_t w, const Nb& n)
 // so those sites compare the complement of their uniform with U_|k| (the
 // planes and the low half xored with neg) and take the opposite result.  The
 // k = 0 sites are decided by the top bit of x alone.
-__device__ __forceinline__ uint32_t heatbath_mask(uint32_t w, const Nb& n, uint32_t v, const PhiloxHalf& ph,
+template <class BLK>
+__device__ __forceinline__ uint32_t heatbath_mask(uint32_t w, const Nb& n, uint32_t v, const BLK& blk,
                                                   const SweepArgs& a)
 {
     const HbClass c = hb_classes(w, n);
     uint32_t eq = ~c.zero;
     // blocks 0, 1 and 2 together (three independent chains), as in accept_mask
-    const U4 P0 = philox10_h(4u * v, a.tag | kStreamSweepHigh, ph, a.key0, a.key1);
-    const U4 P1 = philox10_h(4u * v + 1u, a.tag | kStreamSweepHigh, ph, a.key0, a.key1);
-    const U4 P2 = philox10_h(4u * v + 2u, a.tag | kStreamSweepHigh, ph, a.key0, a.key1);
+    const U4 P0 = blk(4u * v, a.tag | kStreamSweepHigh);
+    const U4 P1 = blk(4u * v + 1u, a.tag | kStreamSweepHigh);
+    const U4 P2 = blk(4u * v + 2u, a.tag | kStreamSweepHigh);
     const uint32_t pl[12] = {P0.x, P0.y, P0.z, P0.w, P1.x, P1.y, P1.z, P1.w, P2.x, P2.y, P2.z, P2.w};
     uint32_t acc = c.zero & ~pl[0];  // U_0 = 2^31: x < U_0 iff its top bit is 0
 #pragma unroll
@@ -454,7 +475,7 @@ __device__ __forceinline__ uint32_t heatbath_mask(uint32_t w, const Nb& n, uint3
 #pragma unroll
     for (int kk = 3; kk < 4; ++kk) {
         if (!__any(eq != 0u)) break;
-        const U4 P = philox10_h(4u * v + (uint32_t)kk, a.tag | kStreamSweepHigh, ph, a.key0, a.key1);
+        const U4 P = blk(4u * v + (uint32_t)kk, a.tag | kStreamSweepHigh);
         const uint32_t pq[4] = {P.x, P.y, P.z, P.w};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -469,7 +490,7 @@ __device__ __forceinline__ uint32_t heatbath_mask(uint32_t w, const Nb& n, uint3
             const int b = __builtin_ctz(tie);
             tie &= tie - 1u;
             const uint32_t q = 32u * v + (uint32_t)b;
-            const U4 P = philox10_h(q >> 3, a.tag | kStreamSweepLow, ph, a.key0, a.key1);
+            const U4 P = blk(q >> 3, a.tag | kStreamSweepLow);
             const uint32_t word = pick(P, (q >> 1) & 3u);
             uint32_t lo = (q & 1u) ? (word & 0xFFFFu) : (word >> 16);
             if ((c.neg >> b) & 1u) lo ^= 0xFFFFu;
@@ -553,14 +574,20 @@ __device__ __forceinline__ void half_sweep(uint32_t (&own)[Geo<L>::K], const uin
 {
     using Gm = Geo<L>;
     const Neighbours<L, C> nb(oth, lane, gl);
-    const PhiloxHalf ph = philox_half(2u * g + (uint32_t)C, j, a.key0);
+    const uint32_t ctr1 = 2u * g + (uint32_t)C;
+    const auto blocks = [&]() {
+        if constexpr (Gm::REPW == 1)
+            return HalfBlocks{philox_half(ctr1, j, a.key0), a.key0, a.key1};
+        else
+            return PlainBlocks{ctr1, j, a.key0, a.key1};
+    }();
 #pragma unroll
     for (int k = 0; k < Gm::K; ++k) {
         const uint32_t v = (uint32_t)(gl * Gm::K + k);
         if constexpr (HB)
-            own[k] ^= heatbath_mask(own[k], nb.get(oth, k), v, ph, a);
+            own[k] ^= heatbath_mask(own[k], nb.get(oth, k), v, blocks, a);
         else
-            own[k] ^= accept_mask(own[k], nb.get(oth, k), v, ph, a);
+            own[k] ^= accept_mask(own[k], nb.get(oth, k), v, blocks, a);
     }
 }
 
