@@ -253,12 +253,13 @@ pa_status pa_upload_population(pa_run* r, int32_t R_cur, const int8_t* spins, in
 pa_status pa_download_counts(pa_run* r, uint32_t* counts, int32_t* n);
 
 /* Test hook for the sweeps of L >= 128, which keep each replica in LDS and
- * queue the sites whose uniform still ties with the threshold after its 8
- * high bits, to be decided one per lane (Sec. 3, spin updates).  When more
- * sites are tied than the queue holds (256 entries), every lane decides its own
- * tied sites instead.  cap >= 0 lowers the number of entries a wave may use
- * before taking that second route (0: always), so that tests reach it; values
- * of 256 and above restore the default.  Results do not depend on cap.
+ * queue the words that hold a site whose uniform still ties with the
+ * threshold after its 8 high bits, each word to be decided by one lane (Sec.
+ * 3, spin updates).  When more words are queued than the queue holds (128
+ * entries), every lane decides its own tied sites instead.  cap >= 0 lowers
+ * the number of entries a wave may use before taking that second route (0:
+ * always), so that tests reach it; values of 128 and above restore the
+ * default.  Results do not depend on cap.
  * Errors: PA_EINVAL (cap < 0), PA_ESTATE. */
 pa_status pa_set_tie_queue_cap(pa_run* r, int32_t cap);
 

@@ -361,8 +361,9 @@ class Run:
         return buf[: n.value].copy()
 
     def set_tie_queue_cap(self, cap):
-        """Limit the LDS-path tie queue to cap entries (0: every lane decides
-        its own ties); 256 or more restores the default."""
+        """Limit the LDS-path tie queue to cap entries, one per word with a
+        tied site (0: every lane decides its own ties); 128 or more restores
+        the default."""
         _check(lib().pa_set_tie_queue_cap(self.h, int(cap)), self.h)
 
 

@@ -224,12 +224,13 @@ struct Geo {
     static constexpr int RPW = WIDE ? 1 : 32 / HW;    // rows per word (narrow)
     static constexpr size_t BITS_BYTES = N / 8;       // bytes per replica, bit store
     static constexpr int RPWV = (K == 1) ? REPW : 1;  // replicas per wave
-    // LDS path: a lane decides up to 8 of its K words before the sites still
-    // tied are resolved through the wave's tie queue (QCAP entries).
+    // LDS path: a lane decides up to 8 of its K words before the words with
+    // sites still tied are resolved through the wave's tie queue (QCAP entries
+    // of four words each).
     static constexpr int SLOTS = (K == 1) ? 1 : (K < 8 ? K : 8);
-    static constexpr int QCAP = 256;
-    // LDS words of one wave on the LDS path: replica [2][NW], queue, slot results
-    static constexpr int WAVE_LDS_WORDS = (K == 1) ? 0 : 2 * NW + QCAP + SLOTS * 64;
+    static constexpr int QCAP = 128;
+    // LDS words of one wave on the LDS path: replica [2][NW], then the queue
+    static constexpr int WAVE_LDS_WORDS = (K == 1) ? 0 : 2 * NW + 4 * QCAP;
     static constexpr int lds_words(int wpb) { return wpb * WAVE_LDS_WORDS; }
     static_assert(L % 16 == 0 && L >= 16 && L <= 256, "lattice size");
     static_assert(K >= 1 && NW % G == 0, "lane mapping");
@@ -600,7 +601,7 @@ __device__ __forceinline__ void half_sweep(uint32_t (&own)[Geo<L>::K], const uin
 // two threshold bits, shared by the NG words: 2-3 operations per word and
 // plane.  The words are updated with their decided flips; `tie` receives the
 // sites whose 8 high bits equal the threshold's (probability 2^-8 each),
-// decided later by decide_tail.  With HB (heat-bath, the update of
+// decided later by decide_word_tail.  With HB (heat-bath, the update of
 // heatbath_mask) every site draws, the k = 0 sites are decided by plane 0, the
 // k < 0 sites compare the complemented planes (`ng`) and are flipped
 // provisionally, so that the tail's result xored on top gives their decision.
@@ -692,43 +693,6 @@ __device__ __forceinline__ void decide8_group(uint32_t (&w)[NG], const Nb (&n)[N
     }
 }
 
-// Remaining comparison of site b of word v, tied after 8 planes: planes 8..15
-// (Philox blocks 2 and 3, four planes each, compared as nibbles), then the low
-// 16 bits from the SWEEP-LOW stream.  True if the uniform is below the
-// threshold; with ng (heat-bath, k < 0) the uniform's complement is compared.
-__device__ __forceinline__ bool decide_tail(uint32_t v, uint32_t b, bool k2, bool ng, uint32_t ctr1, uint32_t j,
-                                            const SweepArgs& a)
-{
-    const uint32_t th = k2 ? a.t2h : a.t4h;
-    const uint32_t flip = ng ? 0xFFFFu : 0u;
-#pragma unroll
-    for (int kk = 2; kk < 4; ++kk) {
-        const U4 P = philox10u(4u * v + (uint32_t)kk, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
-        const uint32_t x = ((((P.x >> b) & 1u) << 3) | (((P.y >> b) & 1u) << 2) | (((P.z >> b) & 1u) << 1) |
-                            ((P.w >> b) & 1u)) ^ (flip & 15u);
-        const uint32_t t = (th >> (12 - 4 * kk)) & 15u;
-        if (x != t) return x < t;
-    }
-    const uint32_t q = 32u * v + b;
-    const U4 P = philox10u(q >> 3, ctr1, j, a.tag | kStreamSweepLow, a.key0, a.key1);
-    const uint32_t word = pick(P, (q >> 1) & 3u);
-    const uint32_t lo = ((q & 1u) ? (word & 0xFFFFu) : (word >> 16)) ^ flip;
-    return lo < (k2 ? a.t2l : a.t4l);
-}
-
-// Exclusive prefix sum over the 64 lanes of the wave; *total gets the sum.
-__device__ __forceinline__ uint32_t wave_prefix(uint32_t x, int lane, uint32_t* total)
-{
-    uint32_t incl = x;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = (uint32_t)__shfl_up((int)incl, off);
-        if (lane >= off) incl += y;
-    }
-    *total = (uint32_t)__shfl((int)incl, 63);
-    return incl - x;
-}
-
 // Orders the LDS accesses of one wave: everything before is complete and
 // visible to every lane of the wave after.
 __device__ __forceinline__ void wave_lds_sync()
@@ -738,75 +702,114 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Tie queue of one wave.  The sites still tied after decide8_group are rare (2^-8
-// each), so instead of evaluating the later Philox blocks for every word, the
-// tied sites of the S words of every lane are queued in LDS and decided one per
-// lane.  An entry is  bits 0-4 site | bit 5 class k = 2 | bits 6-11 lane |
-// bits 12-15 slot | bit 16 complemented uniform (heat-bath, k < 0)  (slot: which
-// of the lane's S words); the decisions are ORed into res[slot * 64 + lane].
-__device__ __forceinline__ uint32_t tie_entry(int s, int lane, uint32_t k2bit, uint32_t ngbit, uint32_t b)
+// Remaining comparison of the tied sites `mask` of word v (all tied after 8
+// planes): Philox block 2 (planes 8-11) once for the word, block 3 (planes
+// 12-15) once if a site is still tied, then the SWEEP-LOW half of each site
+// still tied.  k2m marks the sites of class k = 2, ngm those that compare the
+// complement of their uniform (heat-bath, k < 0).  Returns the sites whose
+// (complemented) uniform is below their threshold, each decided exactly as a
+// comparison of its whole 32-bit uniform would decide it.
+__device__ __forceinline__ uint32_t decide_word_tail(uint32_t v, uint32_t mask, uint32_t k2m, uint32_t ngm,
+                                                     uint32_t ctr1, uint32_t j, const SweepArgs& a)
 {
-    return (ngbit << 16) | ((uint32_t)s << 12) | ((uint32_t)lane << 6) | (k2bit << 5) | b;
+    uint32_t below = 0u;
+#pragma unroll
+    for (int kk = 2; kk < 4; ++kk) {
+        if (mask == 0u) return below;
+        const U4 P = philox10u(4u * v + (uint32_t)kk, ctr1, j, a.tag | kStreamSweepHigh, a.key0, a.key1);
+        uint32_t rem = mask;
+        while (rem) {
+            const uint32_t b = (uint32_t)__builtin_ctz(rem);
+            rem &= rem - 1u;
+            const uint32_t th = ((k2m >> b) & 1u) ? a.t2h : a.t4h;
+            const uint32_t x = ((((P.x >> b) & 1u) << 3) | (((P.y >> b) & 1u) << 2) | (((P.z >> b) & 1u) << 1) |
+                                ((P.w >> b) & 1u)) ^ (((ngm >> b) & 1u) * 15u);
+            const uint32_t t = (th >> (12 - 4 * kk)) & 15u;
+            if (x != t) {
+                mask &= ~(1u << b);
+                if (x < t) below |= 1u << b;
+            }
+        }
+    }
+    while (mask) {
+        const uint32_t b = (uint32_t)__builtin_ctz(mask);
+        mask &= mask - 1u;
+        const uint32_t q = 32u * v + b;
+        const U4 P = philox10u(q >> 3, ctr1, j, a.tag | kStreamSweepLow, a.key0, a.key1);
+        const uint32_t word = pick(P, (q >> 1) & 3u);
+        const uint32_t lo = ((q & 1u) ? (word & 0xFFFFu) : (word >> 16)) ^ (((ngm >> b) & 1u) * 0xFFFFu);
+        if (lo < (((k2m >> b) & 1u) ? a.t2l : a.t4l)) below |= 1u << b;
+    }
+    return below;
 }
 
-// Tie resolution of the wave: queue[QCAP], res[S * 64] (zero on entry and on
-// return).  vj(lane, slot, &v, &j) gives the word and replica of a lane's
-// slot; ng[s] marks the sites that compare the complement of their uniform
-// (heat-bath, k < 0; all zero for Metropolis); extra[s] receives the
-// additional flips of the lane's word s.  If the queue would hold more than
-// min(a.qcap, QCAP) entries, every lane decides its own tied sites instead.
-template <int S, int QCAP, class VJ>
+// Tie queue of one wave.  The sites still tied after decide8_group are rare
+// (2^-8 each), so instead of evaluating the later Philox blocks for every
+// word, every word of the lanes' S words that holds a tied site is queued in
+// LDS and decided by one lane, which evaluates the later blocks once for all
+// of the word's tied sites.  Entry i of the queue is four words:
+//   queue[i]            lane | slot << 6   (slot: which of the lane's S words)
+//   queue[Q + i]        the word's tied sites
+//   queue[2 Q + i]      the tied sites of class k = 2
+//   queue[3 Q + i]      the tied sites that compare the complement of their
+//                       uniform (heat-bath, k < 0)
+// with Q = QCAP.  Each slot's entries are placed by a wave vote: the lanes with
+// a tie in that slot take consecutive entries in lane order.
+//
+// vj(lane, slot, &v, &j) gives the word and replica of a lane's slot, and
+// word(lane, slot) the LDS address of that word, into which the resolving lane
+// xors the additional flips (each word is in one entry, so no two lanes touch
+// the same word).  If the queue would hold more than min(a.qcap, QCAP)
+// entries, every lane decides its own tied sites instead and extra[s] receives
+// its additional flips (zero otherwise).
+template <int S, int QCAP, class VJ, class WORD>
 __device__ __forceinline__ void resolve_ties_wave(const uint32_t (&tie)[S], const uint32_t (&cls1)[S],
                                                   const uint32_t (&ng)[S], int lane, uint32_t ctr1, const SweepArgs& a,
-                                                  uint32_t* queue, uint32_t* res, uint32_t (&extra)[S], const VJ& vj)
+                                                  uint32_t* queue, uint32_t (&extra)[S], const VJ& vj, const WORD& word)
 {
     const uint32_t cap = min(a.qcap, (uint32_t)QCAP);
+    uint64_t vote[S];
+    uint32_t total = 0u;
 #pragma unroll
-    for (int s = 0; s < S; ++s) extra[s] = 0u;
-    uint32_t cnt = 0;
-#pragma unroll
-    for (int s = 0; s < S; ++s) cnt += __popc(tie[s]);
-    uint32_t total;
-    uint32_t off = wave_prefix(cnt, lane, &total);
+    for (int s = 0; s < S; ++s) {
+        extra[s] = 0u;
+        vote[s] = __ballot(tie[s] != 0u);
+        total += (uint32_t)__popcll(vote[s]);
+    }
     if (total == 0u) return;
     if (total > cap) {
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            uint32_t t = tie[s];
+            if (tie[s] == 0u) continue;
             uint32_t v, j;
             vj(lane, s, &v, &j);
-            while (t) {
-                const uint32_t b = (uint32_t)__builtin_ctz(t);
-                t &= t - 1u;
-                if (decide_tail(v, b, (cls1[s] >> b) & 1u, (ng[s] >> b) & 1u, ctr1, j, a)) extra[s] |= 1u << b;
-            }
+            extra[s] = decide_word_tail(v, tie[s], cls1[s] & tie[s], ng[s] & tie[s], ctr1, j, a);
         }
         return;
     }
+    uint32_t base = 0u;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        uint32_t t = tie[s];
-        while (t) {
-            const uint32_t b = (uint32_t)__builtin_ctz(t);
-            t &= t - 1u;
-            queue[off++] = tie_entry(s, lane, (cls1[s] >> b) & 1u, (ng[s] >> b) & 1u, b);
+        if (tie[s] != 0u) {
+            const uint32_t lo = (uint32_t)vote[s], hi = (uint32_t)(vote[s] >> 32);
+            const uint32_t i = base + __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
+            queue[i] = (uint32_t)lane | ((uint32_t)s << 6);
+            queue[QCAP + i] = tie[s];
+            queue[2 * QCAP + i] = cls1[s] & tie[s];
+            queue[3 * QCAP + i] = ng[s] & tie[s];
         }
+        base += (uint32_t)__popcll(vote[s]);
     }
     wave_lds_sync();
     for (uint32_t i = (uint32_t)lane; i < total; i += 64u) {
         const uint32_t e = queue[i];
-        const int s = (int)((e >> 12) & 15u), owner = (int)((e >> 6) & 63u);
-        const uint32_t b = e & 31u;
+        const int owner = (int)(e & 63u), s = (int)(e >> 6);
         uint32_t v, j;
         vj(owner, s, &v, &j);
-        if (decide_tail(v, b, (e >> 5) & 1u, (e >> 16) & 1u, ctr1, j, a)) atomicOr(&res[s * 64 + owner], 1u << b);
+        const uint32_t f = decide_word_tail(v, queue[QCAP + i], queue[2 * QCAP + i], queue[3 * QCAP + i], ctr1, j, a);
+        if (f) atomicXor(word(owner, s), f);
     }
     wave_lds_sync();
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        extra[s] = res[s * 64 + lane];
-        res[s * 64 + lane] = 0u;
-    }
 }
 
 // Sign bits of 64 consecutive int8 spins -> (even-x bits, odd-x bits).
@@ -1015,7 +1018,7 @@ struct LdsRep {
 // SLOTS, each chunk followed by the wave's tie resolution.
 template <int L, int C, bool HB>
 __device__ __forceinline__ void half_sweep_lds(const LdsRep<L>& rep, int gl, uint32_t g, uint32_t j,
-                                               const SweepArgs& a, uint32_t* queue, uint32_t* res)
+                                               const SweepArgs& a, uint32_t* queue)
 {
     using Gm = Geo<L>;
     constexpr int S = Gm::SLOTS;
@@ -1052,9 +1055,11 @@ __device__ __forceinline__ void half_sweep_lds(const LdsRep<L>& rep, int gl, uin
             *vo = (uint32_t)(owner * Gm::K + k0 + s);
             *jo = j;
         };
-        resolve_ties_wave<S, Gm::QCAP>(tie, k2, ng, gl, ctr1, a, queue, res, extra, vj);
+        const auto word = [&](int owner, int s) { return &rep.at(C, k0 + s, owner); };
+        resolve_ties_wave<S, Gm::QCAP>(tie, k2, ng, gl, ctr1, a, queue, extra, vj, word);
 #pragma unroll
-        for (int s = 0; s < S; ++s) rep.at(C, k0 + s, gl) ^= extra[s];
+        for (int s = 0; s < S; ++s)
+            if (extra[s]) rep.at(C, k0 + s, gl) ^= extra[s];
     }
     wave_lds_sync();
 }
@@ -1085,10 +1090,7 @@ __device__ __forceinline__ void sweep_lds(const SweepArgs& a, uint32_t j, uint32
     static_assert(Gm::WIDE && Gm::RL % 2 == 0 && Gm::G == 64, "LDS path layout");
     const LdsRep<L> rep{lds};
     uint32_t* queue = lds + 2 * Gm::NW;
-    uint32_t* res = queue + Gm::QCAP;
     const int gl = (int)(threadIdx.x & 63u);
-#pragma unroll
-    for (int s = 0; s < Gm::SLOTS; ++s) res[s * 64 + gl] = 0u;
     const uint8_t* in = a.init ? nullptr : replica_in<L, INT8>(a, j);
 #pragma unroll 1
     for (int k = 0; k < Gm::K; ++k) {
@@ -1110,8 +1112,8 @@ __device__ __forceinline__ void sweep_lds(const SweepArgs& a, uint32_t j, uint32
             half_sweep_lds_lcg<L, 0>(rep, gl, g, j, a);
             half_sweep_lds_lcg<L, 1>(rep, gl, g, j, a);
         } else {
-            half_sweep_lds<L, 0, HB>(rep, gl, g, j, a, queue, res);
-            half_sweep_lds<L, 1, HB>(rep, gl, g, j, a, queue, res);
+            half_sweep_lds<L, 0, HB>(rep, gl, g, j, a, queue);
+            half_sweep_lds<L, 1, HB>(rep, gl, g, j, a, queue);
         }
     }
     uint32_t anti = 0, downs = 0;
