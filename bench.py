@@ -53,17 +53,24 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per sweep launch from the committed counter profile, or None
+def measured_counters():
+    """From the committed counter profile of the sweep: HBM bytes per launch
+    and VALU instructions per 32-site word and half sweep, or (None, None)
     when the kernel source has changed since the counters were taken."""
     import re
     try:
         txt = open(PROFILE).read()
         want = re.search(r"sha256\[:16\] = ([0-9a-f]{16})", txt).group(1)
         val = float(re.search(r"traffic_bytes_per_launch = ([0-9.e+]+)", txt).group(1))
+        valu = float(re.search(r"VALU instructions per 32-site word and half sweep: [^=]*= ([0-9.]+)", txt).group(1))
     except (OSError, AttributeError, ValueError):
-        return None
-    return val if kernel_source_hash() == want else None
+        return None, None
+    return (val, valu) if kernel_source_hash() == want else (None, None)
+
+
+def measured_traffic():
+    """HBM bytes per sweep launch from the committed counter profile (None if stale)."""
+    return measured_counters()[0]
 
 
 def one_run(pa, torch, seed, layout, sweep_events=None):
@@ -569,7 +576,7 @@ def main():
         cal.close()
     head = res[layouts[0]]
     achieved = head["sweep_flips_avg"] * SLOTS_PER_FLIP / (head["sweep_ms_avg"] * 1e-3)
-    traffic = measured_traffic() if args.update == "metropolis" else None
+    traffic, valu_per_word = measured_counters() if args.update == "metropolis" else (None, None)
     # algorithmic HBM bytes of one sweep launch: every replica's spins read and
     # written once for all theta sweeps (N/8 or N bytes each way) plus E and M
     rep_bytes = L * L // 8 if layouts[0] == "bits" else L * L
@@ -606,6 +613,13 @@ def main():
             "unit": "Tops/s (VALU lane-slots, %.1f per attempted flip)" % SLOTS_PER_FLIP,
             "frac": round(achieved / VALU_PEAK_SLOTS, 4),
             "traffic": traffic,
+            # counters of the same kernel (committed profile): VALU instructions per
+            # 32-site word and half sweep, and what they make of the issue peak at
+            # the measured launch time (4 cycles per wave64 instruction)
+            "valu_instr_per_word": valu_per_word,
+            "valu_issue_frac": (round(valu_per_word * head["sweep_flips_avg"] / 32 / 64 * 4
+                                      / (head["sweep_ms_avg"] * 1e-3 * 2.4e9 * 1024), 4)
+                                if valu_per_word else None),
             "hbm_frac": (round(traffic / (head["sweep_ms_avg"] * 1e-3) / HBM_PEAK, 5) if traffic else None),
             "hbm_bytes_algorithmic": round(alg_bytes),
             "hbm_frac_algorithmic": round(alg_bytes / (head["sweep_ms_avg"] * 1e-3) / HBM_PEAK, 5),
