@@ -1,8 +1,8 @@
 """Full-size parity over whole populations and several temperature steps.
 
 * L = 64, R = 20000, theta = 100, fixed dbeta = 0.005 (the headline workload),
-  through pa_anneal, the benchmark's launch configuration: the first two
-  temperature steps, every replica and every observable.
+  through pa_anneal, the benchmark's launch configuration: the first ten
+  temperature steps, every replica and every observable, both stores.
 * L = 128, R = 50000, theta = 50, adaptive steps to alpha* = 0.85 with the
   multi-histogram record (the L = 128 workload): the first three steps, the
   adaptive inverse temperatures bit-equal, every replica, and the reweighted
@@ -67,39 +67,45 @@ def _same_population(g, o, where):
 
 
 @pytest.fixture(scope="module")
-def oracle_l64_two_steps():
-    """Oracle run at L = 64, R = 20000: observables at beta_0 and after each of
-    the first two fixed steps, and the population after each step."""
-    L, R, theta, dbeta = 64, 20000, 100, 0.005
-    print("case oracle L=64 R=20000, two steps, %d threads" % _threads(), flush=True)
+def l64_runs():
+    """The oracle and one GPU run per store at L = 64, R = 20000, compared at
+    beta_0; the tests below advance all three by one fixed step each (one test
+    per step keeps every test well under a minute)."""
+    L, R = 64, 20000
+    print("case l64 r20000, %d oracle threads" % _threads(), flush=True)
     o = oracle.Run(L, R, seed=1)
     o.set_threads(_threads())
     o.init()
-    obs = [o.measure()]
-    pops = []
-    for i in (1, 2):
-        o.resample(i * dbeta)
-        o.sweep(theta)
-        obs.append(o.measure())
-        pops.append(o.get_population())
-        print("  oracle step %d done" % i, flush=True)
-    return obs, pops
+    o0 = o.measure()
+    gpu = {lay: pa.Run(L, R, seed=1, layout=lay) for lay in ("bits", "int8")}
+    for g in gpu.values():
+        _same_obs(g.observables(), o0, "beta0")
+    state = {"o": o, "gpu": gpu, "done": 0}
+    yield state
+    for g in gpu.values():
+        g.close()
 
 
-@pytest.mark.parametrize("layout", ["bits", "int8"])
-def test_l64_r20000_first_two_steps_every_replica(layout, oracle_l64_two_steps):
-    obs, pops = oracle_l64_two_steps
-    print("case l64 r20000 two anneal steps layout=%s" % layout, flush=True)
-    g = pa.Run(64, 20000, seed=1, layout=layout)
-    _same_obs(g.observables(), obs[0], "beta0")
-    for i in (1, 2):
+@pytest.mark.parametrize("step", list(range(1, 11)))
+def test_l64_r20000_first_ten_steps_every_replica(step, l64_runs):
+    """The headline workload (theta = 100, dbeta = 0.005) through pa_anneal, the
+    benchmark's launch configuration, for its first ten temperature steps:
+    every observable and every replica of both stores after each step."""
+    st = l64_runs
+    assert st["done"] == step - 1, "steps run in order"
+    o = st["o"]
+    print("case l64 r20000 step %d" % step, flush=True)
+    o.resample(step * 0.005)
+    o.sweep(100)
+    oo = o.measure()
+    os_, oE, oM = o.get_population()
+    for lay, g in st["gpu"].items():
         got = g.anneal(beta_f=1.0, dbeta=0.005, theta=100, max_steps=1)
         assert len(got) == 1
-        _same_obs(got[0], obs[i], "step %d" % i)
+        _same_obs(got[0], oo, "%s step %d" % (lay, step))
         gs, gE, gM = g.download_population()
-        os_, oE, oM = pops[i - 1]
-        assert np.array_equal(gE, oE) and np.array_equal(gM, oM) and np.array_equal(gs, os_), i
-    g.close()
+        assert np.array_equal(gE, oE) and np.array_equal(gM, oM) and np.array_equal(gs, os_), (lay, step)
+    st["done"] = step
 
 
 @pytest.fixture(scope="module")
