@@ -230,6 +230,9 @@ def observables_static(L, E, M, beta=0.0, lnZ=0.0, lnQ=0.0, stream=None):
         raise PaError(PA_EINVAL, "E and M must be int32 device tensors")
     if E.dim() != 1 or E.shape != M.shape or not E.is_contiguous() or not M.is_contiguous():
         raise PaError(PA_EINVAL, "E and M must be contiguous 1-d tensors of equal length")
+    if E.shape[0] > PA_STATIC_MAX_R:
+        raise PaError(PA_EINVAL, "pa_observables_static takes at most %d replicas (its static device scratch "
+                                 "is sized for that); got %d" % (PA_STATIC_MAX_R, E.shape[0]))
     s = stream if stream is not None else torch.cuda.current_stream(E.device)
     o = Obs()
     with torch.cuda.device(E.device):

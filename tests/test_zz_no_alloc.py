@@ -81,3 +81,6 @@ def test_static_rejects_oversized_population():
                                      0.0, None, ctypes.byref(o)) == pa.PA_EINVAL
     assert lib.pa_observables_static(48, 8, ctypes.c_void_p(p), ctypes.c_void_p(p), 0.0, 0.0, 0.0, None,
                                      ctypes.byref(o)) == pa.PA_EINVAL
+    big = torch.zeros(pa.PA_STATIC_MAX_R + 1, dtype=torch.int32, device="cuda")
+    with pytest.raises(pa.PaError, match="at most"):
+        pa.observables_static(64, big, big)
