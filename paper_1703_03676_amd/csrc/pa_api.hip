@@ -38,7 +38,7 @@ int32_t default_capacity(int32_t R)
 }
 
 struct Layout {
-    size_t spin[2], E[2], M[2], counts, parent, bsum, tbl, stats, parts, mhr, total;
+    size_t spin[2], E[2], M[2], counts, parent, bsum, tbl, stats, parts, acc, mhr, total;
     size_t rep_bytes;   // bytes of one replica
     uint32_t stride;    // interleaved store: bytes per site row (capacity rounded up to 64); else 0
     int32_t capacity, nbins, nblk;
@@ -77,6 +77,7 @@ bool make_layout(const pa_params* p, Layout* lo)
     lo->tbl = take((size_t)lo->nbins * 8);
     lo->stats = take(sizeof(DevStats) + (size_t)lo->nbins * 4);
     lo->parts = take(sizeof(pa::StatsPart) * (size_t)lo->nblk);
+    lo->acc = take(sizeof(pa::AccSlot) * pa::kAccSlots + (size_t)pa::kAccHists * (size_t)lo->nbins * 4);
     lo->mhr = (p->flags & PA_FLAG_MHR) ? take((size_t)lo->nbins * 40) : o;
     lo->total = o;
     return true;
@@ -106,6 +107,8 @@ struct pa_run {
     uint32_t *counts, *parent, *bsum, *tbl, *hist;
     DevStats* stats;
     pa::StatsPart* parts;
+    pa::AccSlot* acc;      // statistics accumulated by the sweep's epilogue (pa_anneal)
+    uint32_t* acc_hist;    // kAccHists histogram copies of nbins bins
     DevMhr mhr;
     // host-side run state
     int64_t R_cur;
@@ -340,6 +343,8 @@ pa_status pa_init(const pa_params* p, void* d_workspace, size_t bytes, void* hip
     r->stats = (DevStats*)(ws + lo.stats);
     r->hist = (uint32_t*)(ws + lo.stats + sizeof(DevStats));
     r->parts = (pa::StatsPart*)(ws + lo.parts);
+    r->acc = (pa::AccSlot*)(ws + lo.acc);
+    r->acc_hist = (uint32_t*)(ws + lo.acc + sizeof(pa::AccSlot) * pa::kAccSlots);
     if (p->flags & PA_FLAG_MHR) {
         uint64_t* m = (uint64_t*)(ws + lo.mhr);
         r->mhr.H = m;
@@ -379,6 +384,10 @@ pa_status pa_init(const pa_params* p, void* d_workspace, size_t bytes, void* hip
     r->version = 1;
     r->stats_version = 0;
     *out = r;
+    {
+        const hipError_t e = pa::launch_acc_reset(r->acc, r->acc_hist, r->nbins, r->stream);
+        if (e != hipSuccess) return fail_hip(r, e, "clear the sweep's statistics accumulators");
+    }
     if (p->flags & PA_FLAG_MHR) {
         pa_status st = PA_OK;
         const hipError_t e = pa::launch_fill_u32((uint32_t*)r->mhr.H, 0u, (size_t)r->nbins * 10, r->stream);
@@ -513,6 +522,11 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
             a.key1 = k1;
             a.tag = tag;
             a.qcap = r->qcap;
+            if (gather) {  // the statistics of the new population in the sweep's epilogue
+                a.acc = r->acc;
+                a.acc_hist = r->acc_hist;
+                a.nbins = r->nbins;
+            }
             const bool hb = (r->p.flags & PA_FLAG_HEATBATH) != 0;
             host::sweep_thresholds(hb, bn, &a.t2h, &a.t2l, &a.t4h, &a.t4l);
             const bool timed = sweep_ms && done < cap;
@@ -521,8 +535,12 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
             if (timed) HIPCHK(hipEventRecord(r->ev_t1, r->stream));
         }
         // (the scatter of queue_resample has cleared the statistics)
-        HIPCHK(pa::launch_stats(r->E[nxt], r->M[nxt], r->lo.capacity, n_dev, r->N, r->stats, r->hist, r->nbins, 0,
-                                r->mhr, r->parts, r->hstats_dev, r->stream));
+        if (gather)
+            HIPCHK(pa::launch_stats_gather(r->acc, r->acc_hist, r->nbins, r->N, r->stats, r->hist, r->hstats_dev,
+                                           r->stream));
+        else
+            HIPCHK(pa::launch_stats(r->E[nxt], r->M[nxt], r->lo.capacity, n_dev, r->N, r->stats, r->hist, r->nbins,
+                                    0, r->mhr, r->parts, r->hstats_dev, r->stream));
         if (sc->mode == PA_STEP_FIXED && bn < sc->beta_f) {
             // while the GPU sweeps: the weights of the next step (its dbeta is
             // known in advance), over the current window plus a margin

@@ -257,6 +257,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sweep_min_w
     a.tag = rd.tag;
     a.qcap = rd.qcap;
     a.stride = 0u;
+    a.acc = nullptr;  // the batch takes its statistics in b_stats
+    a.acc_hist = nullptr;
+    a.nbins = 0;
     a.t2h = st.t2h;
     a.t2l = st.t2l;
     a.t4h = st.t4h;

@@ -929,8 +929,77 @@ __device__ __forceinline__ void store_word(const SweepArgs& a, uint32_t j, uint3
     }
 }
 
+// Epilogue of a sweep launched with a.acc: the wave's replicas (E, M on the
+// first lane of each valid group) are added to the population statistics,
+// slot and histogram copy chosen by the wave's index.  The moment sums are
+// summed over the wave first, so one lane issues one atomic per quantity; the
+// energies go to the histogram copy with one atomic per distinct bin of the
+// wave.  Integer sums, so the result does not depend on the order in which
+// waves finish.  Called by every lane of the wave.
+template <int L>
+__device__ __forceinline__ void accumulate_stats(const SweepArgs& a, const LaneInfo& li, int32_t e, int32_t m)
+{
+    using Gm = Geo<L>;
+    const bool lead = li.valid && li.gl == 0;
+    uint64_t sE = 0, sE2 = 0, sA = 0, sM2 = 0, q_lo = 0, q_hi = 0;
+    int32_t emin = 0x7FFFFFFF, emax = (int32_t)0x80000000;
+    int b = 0;
+    if (lead) {
+        const int64_t e64 = e;
+        const uint64_t am = (uint64_t)(m < 0 ? -(int64_t)m : (int64_t)m);
+        const uint64_t m2 = am * am;                 // <= 2^32
+        const uint64_t p_lo = m2 * m2, p_hi = __umul64hi(m2, m2);  // M^4 <= 2^64
+        sE = (uint64_t)e64;
+        sE2 = (uint64_t)(e64 * e64);
+        sA = am;
+        sM2 = m2;
+        q_lo = p_lo & 0xFFFFFFFFull;
+        q_hi = (p_lo >> 32) | (p_hi << 32);
+        emin = emax = e;
+        b = (e + 2 * Gm::N) >> 2;  // in [0, N] for |E| <= 2N
+    }
+    if constexpr (Gm::REPW > 1) {
+#pragma unroll
+        for (int off = 32; off >= Gm::G; off >>= 1) {
+            sE += __shfl_xor(sE, off);
+            sE2 += __shfl_xor(sE2, off);
+            sA += __shfl_xor(sA, off);
+            sM2 += __shfl_xor(sM2, off);
+            q_lo += __shfl_xor(q_lo, off);
+            q_hi += __shfl_xor(q_hi, off);
+            emin = min(emin, __shfl_xor(emin, off));
+            emax = max(emax, __shfl_xor(emax, off));
+        }
+    }
+    const uint32_t w = (uint32_t)__builtin_amdgcn_readfirstlane((int)(li.j / (uint32_t)Gm::REPW));
+    if (li.lane == 0 && __builtin_amdgcn_readfirstlane((int)(emin <= emax))) {
+        AccSlot* s = a.acc + (w % (uint32_t)kAccSlots);
+        atomicAdd((unsigned long long*)&s->sumE, (unsigned long long)sE);
+        atomicAdd((unsigned long long*)&s->sumE2, (unsigned long long)sE2);
+        atomicAdd((unsigned long long*)&s->sumAbsM, (unsigned long long)sA);
+        atomicAdd((unsigned long long*)&s->sumM2, (unsigned long long)sM2);
+        atomicAdd((unsigned long long*)&s->m4lo, (unsigned long long)q_lo);
+        atomicAdd((unsigned long long*)&s->m4hi, (unsigned long long)q_hi);
+        atomicMin(&s->emin, emin);
+        atomicMax(&s->emax, emax);
+    }
+    uint32_t* h = a.acc_hist + (size_t)(w % (uint32_t)kAccHists) * (size_t)a.nbins;
+    if constexpr (Gm::REPW == 1) {
+        if (li.lane == 0 && lead) atomicAdd(&h[b], 1u);
+    } else {
+        uint64_t pending = __ballot(lead);
+        while (pending) {
+            const int leader = __builtin_ctzll(pending);
+            const int bv = __builtin_amdgcn_readlane(b, leader);
+            const uint64_t same = __ballot(lead && b == bv);
+            if (li.lane == leader) atomicAdd(&h[bv], (uint32_t)__popcll(same));
+            pending &= ~same;
+        }
+    }
+}
+
 // E = 2 (anti-aligned bonds) - 2N and M = N - 2 (down spins), written by the
-// first lane of the replica's group.
+// first lane of the replica's group; with a.acc the epilogue above follows.
 template <int L>
 __device__ __forceinline__ void write_EM(const SweepArgs& a, const LaneInfo& li, uint32_t anti, uint32_t downs)
 {
@@ -940,10 +1009,12 @@ __device__ __forceinline__ void write_EM(const SweepArgs& a, const LaneInfo& li,
         anti += (uint32_t)__shfl_xor((int)anti, off);
         downs += (uint32_t)__shfl_xor((int)downs, off);
     }
+    const int32_t e = 2 * (int32_t)anti - 2 * Gm::N, m = Gm::N - 2 * (int32_t)downs;
     if (li.valid && li.gl == 0) {
-        a.E[li.j] = 2 * (int32_t)anti - 2 * Gm::N;
-        a.M[li.j] = Gm::N - 2 * (int32_t)downs;
+        a.E[li.j] = e;
+        a.M[li.j] = m;
     }
+    if (a.acc) accumulate_stats<L>(a, li, e, m);
 }
 
 // Register-resident sweep: each lane owns one word per colour (L <= 64).

@@ -26,6 +26,23 @@ struct StatsPart {
 };
 static_assert(sizeof(StatsPart) == 64, "partial statistics layout");
 
+// Statistics taken in the sweep's epilogue: every wave adds the moment sums
+// and the energy range of its replicas to slot (w mod kAccSlots) and their
+// energies to histogram copy (w mod kAccHists), w being the wave's index in
+// the launch, with device atomics spread over that many addresses so that
+// they seldom meet; a gather pass sums slots and copies into the DevStats
+// block and the histogram and leaves them cleared for the next sweep.  M^4
+// (up to 2^64) is split so that both of its sums fit 64 bits: m4lo adds its
+// low 32 bits, m4hi the rest (M^4 >> 32).
+constexpr int kAccSlots = 256;
+constexpr int kAccHists = 16;
+struct AccSlot {
+    uint64_t sumE, sumE2, sumAbsM, sumM2, m4lo, m4hi;
+    int32_t emin, emax;
+    uint64_t pad[9];  // one 128-byte cache line per slot
+};
+static_assert(sizeof(AccSlot) == 128, "accumulator slot layout");
+
 // Per-energy accumulators for multi-histogram reweighting (device resident).
 struct DevMhr {
     uint64_t* H;        // [nbins] number of measured replicas per energy
@@ -53,6 +70,9 @@ struct SweepArgs {
     const uint32_t* parent; // (the resampling copy fused into the sweep's load); else NULL
     uint32_t stride;        // interleaved store: bytes from one site's row of spins (one byte per
                             // replica) to the next, the capacity rounded up to 64; 0 for the other stores
+    AccSlot* acc;           // if set: the sweep's epilogue adds the population statistics to these
+    uint32_t* acc_hist;     // kAccSlots slots and kAccHists histogram copies of nbins bins each
+    int32_t nbins;          // (bit-sliced kernels only)
 };
 
 constexpr int kBlock = 256;     // threads per block of the population kernels

@@ -3,6 +3,7 @@
 //
 //   stats_kernel   energy histogram, energy range and exact moment sums
 //                  (inputs of Eq. (Q), Eq. (observables), multi-histogram)
+//   stats_gather   the same statistics from the sweep epilogue's accumulators
 //   counts_kernel  integer copy counts, Eq. (resampling factors), block totals
 //   scatter        prefix sum of the counts -> parent index of every child
 //   copy_kernel    replica copy into the other half of the ping-pong store
@@ -83,6 +84,82 @@ __global__ void stats_reset_kernel(DevStats* st, uint32_t* hist, int32_t nbins)
         st->sumE = st->sumE2 = st->sumAbsM = st->sumM2 = st->sumM4_lo = st->sumM4_hi = 0;
     }
     for (int b = i; b < nbins; b += (int)(gridDim.x * blockDim.x)) hist[b] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Statistics accumulated by the sweep's epilogue (AccSlot): one block sums the
+// kAccSlots slots into *st (M^4 rebuilt as a 128-bit sum), then the
+// kAccHists histogram copies over the occupied window [emin, emax] into hist,
+// resetting every slot and bin it reads (sums 0, empty range, bins 0) for the
+// next sweep.  hist has been cleared before (by the scatter) and r_new is
+// kept.  With `host` the statistics block and the window are published there
+// as stats_kernel does.
+// ---------------------------------------------------------------------------
+constexpr int kGatherThreads = 1024;
+static_assert(kAccSlots <= kGatherThreads, "one slot per thread");
+
+__device__ __forceinline__ void reset_slot(AccSlot* s)
+{
+    s->sumE = s->sumE2 = s->sumAbsM = s->sumM2 = s->m4lo = s->m4hi = 0;
+    s->emin = 0x7FFFFFFF;
+    s->emax = (int32_t)0x80000000;
+}
+
+__global__ __launch_bounds__(kGatherThreads) void stats_gather_kernel(AccSlot* __restrict__ acc,
+                                                                      uint32_t* __restrict__ acc_hist, int32_t nbins,
+                                                                      int32_t N, DevStats* st,
+                                                                      uint32_t* __restrict__ hist,
+                                                                      uint32_t* __restrict__ host)
+{
+    __shared__ DevStats sh;
+    const int t = (int)threadIdx.x;
+    const uint32_t r_new = st->r_new;  // from the scatter
+    uint64_t sE = 0, sE2 = 0, sA = 0, sM2 = 0, m4lo = 0, m4hi = 0;
+    int32_t emin = 0x7FFFFFFF, emax = (int32_t)0x80000000;
+    if (t < kAccSlots) {
+        AccSlot* s = acc + t;
+        sE = s->sumE;
+        sE2 = s->sumE2;
+        sA = s->sumAbsM;
+        sM2 = s->sumM2;
+        const uint64_t low32 = s->m4lo, rest = s->m4hi;  // M^4 sum = rest * 2^32 + low32
+        m4lo = rest << 32;
+        m4hi = rest >> 32;
+        add_u128(m4lo, m4hi, low32, 0u);
+        emin = s->emin;
+        emax = s->emax;
+        reset_slot(s);
+    }
+    stats_block_total<kGatherThreads>(sE, sE2, sA, sM2, m4lo, m4hi, emin, emax, st, &sh);
+    __syncthreads();  // the totals in sh, written by thread 0, are visible to the block
+    const int32_t lo = sh.emin, hi = sh.emax;
+    if (host && t < (int)(sizeof(DevStats) / 4)) {
+        const uint32_t* sw = reinterpret_cast<const uint32_t*>(&sh);
+        host[t] = (t == 2) ? r_new : (t == 3) ? 0u : sw[t];
+    }
+    if (lo > hi || lo < -2 * N || hi > 2 * N) return;  // empty: no bins were added
+    uint32_t* hh = host ? host + sizeof(DevStats) / 4 : nullptr;
+    for (int b = (lo + 2 * N) / 4 + t; b <= (hi + 2 * N) / 4; b += kGatherThreads) {
+        uint32_t c[kAccHists];
+#pragma unroll
+        for (int k = 0; k < kAccHists; ++k) c[k] = acc_hist[(size_t)k * nbins + b];
+        uint32_t v = 0;
+#pragma unroll
+        for (int k = 0; k < kAccHists; ++k) {
+            v += c[k];
+            acc_hist[(size_t)k * nbins + b] = 0u;
+        }
+        hist[b] = v;
+        if (hh) hh[b] = v;
+    }
+}
+
+// Every slot to the empty state and every histogram copy to zero.
+__global__ void acc_reset_kernel(AccSlot* acc, uint32_t* acc_hist, size_t nh)
+{
+    const size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x;
+    if (i < (size_t)kAccSlots) reset_slot(acc + i);
+    for (size_t k = i; k < nh; k += (size_t)gridDim.x * blockDim.x) acc_hist[k] = 0u;
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t value, size_t n)
@@ -253,6 +330,23 @@ hipError_t launch_stats_reset(DevStats* st, uint32_t* hist, int32_t nbins, hipSt
 {
     const int blocks = std::min((nbins + kBlock - 1) / kBlock, 1024);
     hipLaunchKernelGGL(stats_reset_kernel, dim3(std::max(blocks, 1)), dim3(kBlock), 0, s, st, hist, nbins);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats_gather(AccSlot* acc, uint32_t* acc_hist, int32_t nbins, int32_t N, DevStats* st,
+                               uint32_t* hist, void* host, hipStream_t s)
+{
+    hipLaunchKernelGGL(stats_gather_kernel, dim3(1), dim3(kGatherThreads), 0, s, acc, acc_hist, nbins, N, st, hist,
+                       (uint32_t*)host);
+    return hipGetLastError();
+}
+
+hipError_t launch_acc_reset(AccSlot* acc, uint32_t* acc_hist, int32_t nbins, hipStream_t s)
+{
+    const size_t nh = (size_t)kAccHists * (size_t)nbins;
+    const size_t blocks = std::min<size_t>((nh + kBlock - 1) / kBlock, 4096);
+    hipLaunchKernelGGL(acc_reset_kernel, dim3((unsigned)std::max<size_t>(blocks, 1)), dim3(kBlock), 0, s, acc,
+                       acc_hist, nh);
     return hipGetLastError();
 }
 

@@ -43,6 +43,13 @@ hipError_t launch_sweep_rp(int L, int update, const SweepArgs& a, hipStream_t s)
 hipError_t launch_copy_rp(const uint8_t* src, const int32_t* Esrc, const int32_t* Msrc, const uint32_t* parent,
                           const uint32_t* n_new, int32_t cap, int32_t N, uint32_t stride, uint8_t* dst, int32_t* Edst,
                           int32_t* Mdst, hipStream_t s);
+// Statistics of the population a sweep launched with SweepArgs::acc has just
+// swept: the epilogue's accumulators summed into st and the histogram window
+// (hist cleared before, r_new kept), published to `host` as by launch_stats,
+// and the accumulators left cleared.  launch_acc_reset clears them once.
+hipError_t launch_stats_gather(AccSlot* acc, uint32_t* acc_hist, int32_t nbins, int32_t N, DevStats* st,
+                               uint32_t* hist, void* host, hipStream_t s);
+hipError_t launch_acc_reset(AccSlot* acc, uint32_t* acc_hist, int32_t nbins, hipStream_t s);
 // Clears the range, the sums and the histogram (not r_new).
 hipError_t launch_stats_reset(DevStats* st, uint32_t* hist, int32_t nbins, hipStream_t s);
 

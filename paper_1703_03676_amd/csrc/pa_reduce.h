@@ -184,25 +184,17 @@ __device__ __forceinline__ void stats_block(const int32_t* __restrict__ E, const
     }
 }
 
-// Second pass, one block of kBlock threads: sums the nparts partials into st
-// (energy range and moment sums; r_new is left as it is).
-__device__ __forceinline__ void stats_final(const StatsPart* __restrict__ parts, int32_t nparts, DevStats* st)
+// Sums per-thread statistics over one block of NT threads into st (energy
+// range and moment sums; r_new and done are left as they are), and into the
+// block's LDS copy `sh` if given.  Called by every thread of the block.
+template <int NT>
+__device__ __forceinline__ void stats_block_total(uint64_t sE, uint64_t sE2, uint64_t sA, uint64_t sM2,
+                                                  uint64_t m4lo, uint64_t m4hi, int32_t emin, int32_t emax,
+                                                  DevStats* st, DevStats* sh = nullptr)
 {
-    __shared__ uint64_t red[kBlock / 64][6];
-    __shared__ int32_t red_min[kBlock / 64], red_max[kBlock / 64];
+    __shared__ uint64_t red[NT / 64][6];
+    __shared__ int32_t red_min[NT / 64], red_max[NT / 64];
     const int lane = (int)(threadIdx.x & 63u), wid = (int)(threadIdx.x >> 6);
-    uint64_t sE = 0, sE2 = 0, sA = 0, sM2 = 0, m4lo = 0, m4hi = 0;
-    int32_t emin = 0x7FFFFFFF, emax = (int32_t)0x80000000;
-    for (int p = (int)threadIdx.x; p < nparts; p += kBlock) {
-        const StatsPart q = parts[p];
-        sE += q.sumE;
-        sE2 += q.sumE2;
-        sA += q.sumAbsM;
-        sM2 += q.sumM2;
-        add_u128(m4lo, m4hi, q.sumM4_lo, q.sumM4_hi);
-        emin = min(emin, q.emin);
-        emax = max(emax, q.emax);
-    }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         sE += __shfl_xor(sE, off);
@@ -226,7 +218,7 @@ __device__ __forceinline__ void stats_final(const StatsPart* __restrict__ parts,
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < kBlock / 64; ++w) {
+        for (int w = 1; w < NT / 64; ++w) {
             sE += red[w][0];
             sE2 += red[w][1];
             sA += red[w][2];
@@ -243,7 +235,36 @@ __device__ __forceinline__ void stats_final(const StatsPart* __restrict__ parts,
         st->sumM2 = sM2;
         st->sumM4_lo = m4lo;
         st->sumM4_hi = m4hi;
+        if (sh) {
+            sh->emin = emin;
+            sh->emax = emax;
+            sh->sumE = sE;
+            sh->sumE2 = sE2;
+            sh->sumAbsM = sA;
+            sh->sumM2 = sM2;
+            sh->sumM4_lo = m4lo;
+            sh->sumM4_hi = m4hi;
+        }
     }
+}
+
+// Second pass, one block of kBlock threads: sums the nparts partials into st
+// (energy range and moment sums; r_new is left as it is).
+__device__ __forceinline__ void stats_final(const StatsPart* __restrict__ parts, int32_t nparts, DevStats* st)
+{
+    uint64_t sE = 0, sE2 = 0, sA = 0, sM2 = 0, m4lo = 0, m4hi = 0;
+    int32_t emin = 0x7FFFFFFF, emax = (int32_t)0x80000000;
+    for (int p = (int)threadIdx.x; p < nparts; p += kBlock) {
+        const StatsPart q = parts[p];
+        sE += q.sumE;
+        sE2 += q.sumE2;
+        sA += q.sumAbsM;
+        sM2 += q.sumM2;
+        add_u128(m4lo, m4hi, q.sumM4_lo, q.sumM4_hi);
+        emin = min(emin, q.emin);
+        emax = max(emax, q.emax);
+    }
+    stats_block_total<kBlock>(sE, sE2, sA, sM2, m4lo, m4hi, emin, emax, st);
 }
 
 }  // namespace dev

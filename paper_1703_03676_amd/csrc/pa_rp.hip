@@ -266,7 +266,8 @@ hipError_t launch_rp_l(int update, const SweepArgs& a, hipStream_t s)
 
 hipError_t launch_sweep_rp(int L, int update, const SweepArgs& a, hipStream_t s)
 {
-    if (a.parent || a.stride == 0) return hipErrorInvalidValue;  // no fused gather on this store
+    // no fused gather and no statistics epilogue on this store
+    if (a.parent || a.acc || a.stride == 0) return hipErrorInvalidValue;
     switch (L) {
     case 16: return launch_rp_l<16>(update, a, s);
     case 32: return launch_rp_l<32>(update, a, s);

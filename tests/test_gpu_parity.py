@@ -325,6 +325,31 @@ def _fixed_betas(step0, beta0, beta_f, dbeta):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("L,R", [(16, 900), (32, 333), (64, 130), (128, 21), (256, 5)])
+def test_anneal_statistics_from_the_sweep_epilogue(L, R, layout):
+    """pa_anneal takes each step's statistics in the sweep's epilogue (per-wave
+    atomics into accumulator slots and histogram copies, summed by a gather
+    pass that clears them again): every step's sums against the oracle at every
+    lattice size, with partial last waves at L = 16 and 32, over two calls on
+    one run, so leftovers of a step or of a call would show."""
+    print("case anneal epilogue statistics L=%d R=%d layout=%s" % (L, R, layout), flush=True)
+    theta = 2
+    g = pa.Run(L, R, seed=13, layout=layout)
+    o = oracle.Run(L, R, seed=13)
+    o.init()
+    _same_obs(g.observables(), o.measure())
+    got = g.anneal(beta_f=0.3, dbeta=0.1, theta=theta, mode="fixed")
+    got += g.anneal(beta_f=0.6, dbeta=0.1, theta=theta, mode="fixed")
+    want = _fixed_betas(0, 0.0, 0.3, 0.1) + _fixed_betas(3, 0.3, 0.6, 0.1)
+    assert [go["beta"] for go in got] == want
+    for go in got:
+        o.resample(go["beta"])
+        o.sweep(theta)
+        _same_obs(go, o.measure())
+    _same_population(g, o)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 def test_anneal_refusal_in_the_middle_of_a_run(layout):
     """A step refused for capacity after other steps of the same pa_anneal
     call leaves the run at the last completed step, equal to the oracle's;
