@@ -237,9 +237,32 @@ def run_plain_adaptive(pa, L, R_, theta, alpha, beta_f, seed, mhr=False):
     return run, flips, nsteps
 
 
+def anneal_adaptive(pa, torch, L, R_, theta, alpha, seed, mhr=False):
+    """The same adaptive run through pa_anneal (one host round trip per step,
+    the resampling copy fused into the sweep's load, the statistics taken in
+    the sweep's epilogue).  Returns the run, the wall time and the step
+    observables."""
+    run = pa.Run(L, R_, seed=seed, layout="bits", mhr=mhr)
+    run.observables()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    obs = run.anneal(beta_f=1.0, alpha_star=alpha, theta=theta, mode="adaptive")
+    torch.cuda.synchronize()
+    return run, time.perf_counter() - t0, obs
+
+
+def _anneal_line(L, theta, t, obs, plain_last):
+    """Summary of a pa_anneal run, with whether it ended in the plain run's state."""
+    flips = sum(L * L * theta * o["R"] for o in obs)
+    return {"run_wall_time_s": t, "flips_per_ns": flips / (t * 1e9), "temperature_steps": len(obs),
+            "same_final_observables_as_plain": all(obs[-1][k] == plain_last[k]
+                                                   for k in ("beta", "R", "sumE", "sumE2", "sumM4"))}
+
+
 def workload_l128_adaptive(pa, torch):
     """L=128, R=50000, theta=50, adaptive dbeta (alpha*=0.85), multi-histogram
-    reweighting on a 1000-point beta grid; plain single-run form."""
+    reweighting on a 1000-point beta grid; plain single-run form, then the
+    same run through pa_anneal."""
     import numpy as np
     L, R_, theta = 128, 50000, 50
     torch.cuda.synchronize()
@@ -251,12 +274,16 @@ def workload_l128_adaptive(pa, torch):
     rw = run.reweight(np.linspace(0.0, 1.0, 1000))
     t_rw = time.perf_counter() - t1
     last = run.observables()
+    run.close()
+    arun, t_a, obs = anneal_adaptive(pa, torch, L, R_, theta, 0.85, seed=1, mhr=True)
+    arun.close()
     return {
         "workload": "L=128, R=50000, theta=50, adaptive alpha*=0.85, beta 0->1, MHR on 1000 betas",
         "flips_per_ns": flips / (t_run * 1e9), "run_wall_time_s": t_run, "temperature_steps": nsteps,
         "reweight_s": t_rw, "betaF_per_N_final": last["betaF_per_N"],
         "betaF_per_N_exact": _exact_betaF(L, 1.0),
         "mhr_C_peak_beta": float(np.linspace(0.0, 1.0, 1000)[int(np.argmax([o["C"] for o in rw]))]),
+        "pa_anneal": _anneal_line(L, theta, t_a, obs, last),
     }
 
 
@@ -379,9 +406,13 @@ def workload_l256_learned(pa, torch):
     run, flips, nsteps = run_plain_adaptive(pa, L, R_, theta, 0.85, 1.0, seed=5)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    last = run.observables()
     out["plain_adaptive"] = {"run_wall_time_s": t, "flips_per_ns": flips / (t * 1e9), "steps": nsteps,
-                             "betaF_per_N_error": abs(run.observables()["betaF_per_N"] - _exact_betaF(L, 1.0))}
+                             "betaF_per_N_error": abs(last["betaF_per_N"] - _exact_betaF(L, 1.0))}
     run.close()
+    arun, t_a, obs = anneal_adaptive(pa, torch, L, R_, theta, 0.85, seed=5)
+    arun.close()
+    out["pa_anneal_adaptive"] = _anneal_line(L, theta, t_a, obs, last)
     b = pa.Batch([dict(L=L, R=R_, seed=6, layout="bits")],
                  dict(beta_f=1.0, alpha_star=0.85, alpha_tol=0.01, theta=theta, mode="learned"))
     b.set_model(params, norm)
