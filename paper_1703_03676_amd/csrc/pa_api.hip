@@ -119,6 +119,7 @@ struct pa_run {
     bool broken;
     std::string last_error;
     uint64_t version, stats_version;
+    uint64_t gathered_version = 0;  // population whose statistics the last sweep's epilogue publishes to hstats
     DevStats h_stats;
     std::vector<uint32_t> h_hist;
     uint8_t* pinned;
@@ -182,7 +183,12 @@ hipError_t launch_sweep_of(const pa_run* r, pa::SweepArgs& a)
     return pa::launch_sweep(r->L, r->p.layout, update_of(r->p), a, r->stream);
 }
 
-pa_status launch_sweeps(pa_run* r, int32_t nsweeps, bool init)
+// Queues nsweeps sweeps of the current population (or, with `init`, the
+// initial state; with neither, the recount of E and M).  On the bit-sliced
+// stores the sweep takes the population's statistics in its epilogue and the
+// gather publishes them to hstats, so the statistics of population version
+// `ver` need no separate pass (refresh_stats).
+pa_status launch_sweeps(pa_run* r, int32_t nsweeps, bool init, uint64_t ver)
 {
     pa::SweepArgs a;
     std::memset(&a, 0, sizeof(a));
@@ -197,7 +203,19 @@ pa_status launch_sweeps(pa_run* r, int32_t nsweeps, bool init)
     host::sweep_thresholds(hb, r->beta, &a.t2h, &a.t2l, &a.t4h, &a.t4l);
     a.init = init ? 1 : 0;
     a.qcap = r->qcap;
+    const bool epilogue = r->p.layout != PA_SPIN_INTERLEAVED;
+    if (epilogue) {
+        a.acc = r->acc;
+        a.acc_hist = r->acc_hist;
+        a.nbins = r->nbins;
+    }
+    r->gathered_version = 0;
     HIPCHK(launch_sweep_of(r, a));
+    if (epilogue) {
+        HIPCHK(pa::launch_stats_gather(r->acc, r->acc_hist, r->nbins, r->N, r->stats, r->hist, r->hstats_dev,
+                                       r->stream));
+        r->gathered_version = ver;
+    }
     return PA_OK;
 }
 
@@ -225,9 +243,11 @@ Scratch run_scratch(const pa_run* r) { return Scratch{r->counts, r->parent, r->b
 pa_status refresh_stats(pa_run* r, bool record, pa::StatsPart* parts)
 {
     if (!record && r->stats_version == r->version) return PA_OK;
-    HIPCHK(pa::launch_stats_reset(r->stats, r->hist, r->nbins, r->stream));
-    HIPCHK(pa::launch_stats(r->E[r->cur], r->M[r->cur], (int32_t)r->R_cur, nullptr, r->N, r->stats, r->hist,
-                            r->nbins, record ? 1 : 0, r->mhr, parts, r->hstats_dev, r->stream));
+    if (record || r->gathered_version != r->version) {
+        HIPCHK(pa::launch_stats_reset(r->stats, r->hist, r->nbins, r->stream));
+        HIPCHK(pa::launch_stats(r->E[r->cur], r->M[r->cur], (int32_t)r->R_cur, nullptr, r->N, r->stats, r->hist,
+                                r->nbins, record ? 1 : 0, r->mhr, parts, r->hstats_dev, r->stream));
+    }  // else the epilogue of the sweep that made this population has queued them
     HIPCHK(hipStreamSynchronize(r->stream));
     const pa_status st = read_host_stats(r, &r->h_stats);
     if (st != PA_OK) return st;
@@ -394,7 +414,7 @@ pa_status pa_init(const pa_params* p, void* d_workspace, size_t bytes, void* hip
         if (e != hipSuccess) st = fail_hip(r, e, "zero multi-histogram accumulators");
         if (st != PA_OK) return st;
     }
-    return launch_sweeps(r, 0, true);
+    return launch_sweeps(r, 0, true, r->version);
 }
 
 pa_status pa_sweep(pa_run* r, int32_t nsweeps)
@@ -403,7 +423,7 @@ pa_status pa_sweep(pa_run* r, int32_t nsweeps)
     if (st != PA_OK) return st;
     if (nsweeps < 0 || r->sweeps + (uint64_t)nsweeps >= ((uint64_t)1 << 31)) return PA_EINVAL;
     if (nsweeps == 0) return PA_OK;
-    st = launch_sweeps(r, nsweeps, false);
+    st = launch_sweeps(r, nsweeps, false, r->version + 1);
     if (st != PA_OK) return st;
     r->sweeps += (uint64_t)nsweeps;
     r->version += 1;
@@ -534,7 +554,10 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
             HIPCHK(launch_sweep_of(r, a));
             if (timed) HIPCHK(hipEventRecord(r->ev_t1, r->stream));
         }
-        // (the scatter of queue_resample has cleared the statistics)
+        // (the scatter of queue_resample has cleared the statistics); they are
+        // published to hstats, which then no longer holds those of the current
+        // population, even if this step is refused
+        r->gathered_version = 0;
         if (gather)
             HIPCHK(pa::launch_stats_gather(r->acc, r->acc_hist, r->nbins, r->N, r->stats, r->hist, r->hstats_dev,
                                            r->stream));
@@ -770,7 +793,7 @@ pa_status pa_upload_population(pa_run* r, int32_t R_cur, const int8_t* spins, in
     r->lnZ = lnZ;
     r->lnQ_last = 0.0;
     r->version += 1;
-    return launch_sweeps(r, 0, false);  // recount E and M on the device
+    return launch_sweeps(r, 0, false, r->version);  // recount E and M on the device
 }
 
 pa_status pa_download_counts(pa_run* r, uint32_t* counts, int32_t* n)

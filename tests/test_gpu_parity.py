@@ -208,6 +208,36 @@ def test_statistics_windows_and_multi_histogram(L, R, kind, layout):
             assert _close(go[k], oo[k], 1e-12), (k, go["beta"], go[k], oo[k])
 
 
+@pytest.mark.parametrize("layout", LAYOUTS)
+@pytest.mark.parametrize("L,R,kind", [(16, 3000, "mixed"), (64, 700, "ordered"), (64, 700, "mixed"),
+                                      (128, 130, "mixed"), (256, 20, "mixed")])
+def test_statistics_from_the_sweep_epilogue_single_calls(L, R, kind, layout):
+    """Without the multi-histogram record, the statistics of a population made
+    by a sweep (or by the recount after an upload) come from the sweep's
+    epilogue and its gather; after a resampling with no sweep, from the
+    statistics kernel.  Ordered and mixed populations give narrow and very
+    wide energy windows; every measurement matches the oracle."""
+    print("case epilogue stats single calls L=%d R=%d %s layout=%s" % (L, R, kind, layout), flush=True)
+    if kind == "ordered":
+        spins = inputs.ordered_spins(R, L, seed=41, n_flipped_max=40)
+    else:
+        spins = inputs.mixed_spins(R, L, seed=42)
+    g = pa.Run(L, R, seed=23, layout=layout)
+    o = oracle.Run(L, R, seed=23)
+    g.upload_population(spins, step=1, sweeps=3, beta=0.3, lnZ=2.0)
+    o.set_population(spins, step=1, sweeps=3, beta=0.3, lnZ=2.0)
+    _same_obs(g.observables(), o.measure())       # recount's epilogue
+    for beta in (0.32, 0.5):
+        assert g.resample(beta) == o.resample(beta)
+        _same_obs(g.observables(), o.measure())   # statistics kernel
+        g.sweep(2)
+        o.sweep(2)
+        g.sweep(1)                                # two sweeps in a row: only the last one's count
+        o.sweep(1)
+        _same_obs(g.observables(), o.measure())   # the last sweep's epilogue
+    _same_population(g, o)
+
+
 @pytest.mark.parametrize("kind", ["ordered", "mixed"])
 def test_statistics_more_chunks_than_workgroups(kind):
     """The statistics kernel runs a bounded number of workgroups that take
