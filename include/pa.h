@@ -133,7 +133,11 @@ pa_status pa_init(const pa_params* p, void* d_workspace, size_t bytes, void* hip
  * paper's multi-spin-coded variant (Sec. 4): per sweep and per 32-site word of
  * one colour, one Philox draw seeds r' = 1664525 r + 1013904223 mod 2^32, and
  * the word's site b takes the (b+1)-th output; a different Markov chain with
- * the same stationary distribution.  Updates E_j and M_j.  Asynchronous.
+ * the same stationary distribution.  Updates E_j and M_j.  Asynchronous; on
+ * the int8 and bit stores the sweep kernel also queues the statistics of the
+ * swept population (histogram and integer sums), which the next
+ * pa_observables, pa_alpha, pa_adapt_beta or pa_resample reads after waiting
+ * for the stream.
  * Errors: PA_EINVAL (nsweeps < 0), PA_ESTATE, PA_EHIP. */
 pa_status pa_sweep(pa_run* r, int32_t nsweeps);
 

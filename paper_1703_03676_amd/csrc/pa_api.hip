@@ -235,11 +235,13 @@ pa_status read_host_stats(pa_run* r, DevStats* out)
     return PA_OK;
 }
 
-// Brings the histogram and the integer sums of the current population to the
-// host.  With `record` the measurement is also added to the multi-histogram
-// accumulators (only then is a cached result not reused).
 Scratch run_scratch(const pa_run* r) { return Scratch{r->counts, r->parent, r->bsum, r->tbl, r->parts}; }
 
+// Brings the histogram and the integer sums of the current population to the
+// host: from the host copy if it is current, else from the gather that the
+// epilogue of the sweep which made this population queued, else from the
+// statistics kernel.  With `record` the measurement is also added to the
+// multi-histogram accumulators (only then is a cached result not reused).
 pa_status refresh_stats(pa_run* r, bool record, pa::StatsPart* parts)
 {
     if (!record && r->stats_version == r->version) return PA_OK;
