@@ -605,6 +605,44 @@ def test_capacity_overflow_and_extinction(layout):
 
 
 @pytest.mark.parametrize("layout", LAYOUTS)
+def test_anneal_extinction_keeps_state(layout):
+    """A pa_anneal step that would leave no replica (R = 1 from two equal
+    replicas dies with probability 1/4) sweeps an empty population, whose
+    statistics are empty: the call raises, the run stays at its last step
+    with the oracle's population and statistics, and carries on."""
+    print("case anneal extinction layout=%s" % layout, flush=True)
+    ext = []
+    for seed in range(1, 25):
+        g = pa.Run(16, 1, seed=seed, capacity=8, layout=layout)
+        o = oracle.Run(16, 1, seed=seed, capacity=8)
+        s = np.ones((2, 16, 16), np.int8)
+        g.upload_population(s, step=1, beta=0.1)
+        o.set_population(s, step=1, beta=0.1)
+        try:
+            o.resample(0.2)
+            dead = False
+        except ArithmeticError:
+            dead = True
+        if dead:
+            with pytest.raises(pa.ExtinctError):
+                g.anneal(beta_f=0.2, dbeta=0.1, theta=3)
+            st = g.state()
+            assert st["R"] == 2 and st["step"] == 1 and st["beta"] == 0.1
+            _same_obs(g.observables(), o.measure())
+            g.sweep(2)
+            o.sweep(2)
+            _same_obs(g.observables(), o.measure())
+        else:
+            o.sweep(3)
+            got = g.anneal(beta_f=0.2, dbeta=0.1, theta=3)
+            assert len(got) == 1
+            _same_obs(got[0], o.measure())
+        _same_population(g, o)
+        ext.append(dead)
+    assert any(ext) and not all(ext)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS)
 def test_adaptive_run_and_reweighting(layout):
     """Adaptive steps (alpha* = 0.85) with multi-histogram reweighting."""
     print("case adaptive layout=%s" % layout, flush=True)
