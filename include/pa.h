@@ -267,6 +267,19 @@ pa_status pa_download_counts(pa_run* r, uint32_t* counts, int32_t* n);
  * Errors: PA_EINVAL (cap < 0), PA_ESTATE. */
 pa_status pa_set_tie_queue_cap(pa_run* r, int32_t cap);
 
+/* Test and tuning hook for the population statistics of Sec. 2.1 (energy
+ * histogram and integer moment sums of each new population).  The int8 and
+ * bit stores can take them in the epilogue of the sweep that makes the
+ * population (every wave adds its replicas with device atomics, then one
+ * block sums them) or in a separate pass over E and M.  PA_STATS_AUTO (the
+ * default) takes the epilogue where it measured faster: one replica per wave
+ * (L >= 64) and R <= 32768, or L = 256.  PA_STATS_EPILOGUE and PA_STATS_PASS
+ * force one of them (the interleaved store always uses the pass).  Results do
+ * not depend on the choice.
+ * Errors: PA_EINVAL (unknown mode), PA_ESTATE. */
+typedef enum { PA_STATS_AUTO = 0, PA_STATS_EPILOGUE = 1, PA_STATS_PASS = 2 } pa_stats_path;
+pa_status pa_set_stats_path(pa_run* r, int32_t mode);
+
 /* ---- Batched runs: many independent PA runs advanced together. ----------
  * Every run has its own parameters (L, R, seed, run_id, layout, flags) and
  * schedule.  One pa_batch_step advances every unfinished run by one

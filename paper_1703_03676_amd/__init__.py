@@ -21,6 +21,8 @@ PA_SPIN_INT8, PA_SPIN_BITS, PA_SPIN_INTERLEAVED = 0, 1, 2
 PA_FLAG_MHR = 1
 PA_FLAG_HEATBATH = 2
 PA_FLAG_LCG = 4
+PA_STATS_AUTO, PA_STATS_EPILOGUE, PA_STATS_PASS = 0, 1, 2
+STATS_PATHS = {"auto": PA_STATS_AUTO, "epilogue": PA_STATS_EPILOGUE, "pass": PA_STATS_PASS}
 LAYOUTS = {"int8": PA_SPIN_INT8, "bits": PA_SPIN_BITS, "interleaved": PA_SPIN_INTERLEAVED}
 SUPPORTED_L = (16, 32, 64, 128, 256)
 
@@ -105,6 +107,7 @@ SIGNATURES = {
                                             ctypes.c_double, ctypes.c_double]),
     "pa_download_counts": (ctypes.c_int, [_vp, _vp, _P(ctypes.c_int32)]),
     "pa_set_tie_queue_cap": (ctypes.c_int, [_vp, ctypes.c_int32]),
+    "pa_set_stats_path": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "pa_batch_init_ex": (ctypes.c_int, [_P(Params), _P(Schedule), ctypes.c_int32, _vp, _vp, ctypes.c_size_t, _vp,
                                         _P(_vp)]),
     "pa_batch_waves_per_block": (ctypes.c_int, [_vp, ctypes.c_int32, _P(ctypes.c_int32)]),
@@ -368,6 +371,11 @@ class Run:
         tied site (0: every lane decides its own ties); 128 or more restores
         the default."""
         _check(lib().pa_set_tie_queue_cap(self.h, int(cap)), self.h)
+
+    def set_stats_path(self, path):
+        """Where the statistics of a swept population are taken: "auto",
+        "epilogue" (the sweep's epilogue) or "pass" (a separate pass)."""
+        _check(lib().pa_set_stats_path(self.h, STATS_PATHS.get(path, path)), self.h)
 
 
 def make_schedule(beta_f=1.0, dbeta=0.0, alpha_star=0.0, alpha_tol=0.0, theta=1, mode="fixed", leader=0):

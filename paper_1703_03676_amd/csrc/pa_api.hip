@@ -133,6 +133,7 @@ struct pa_run {
     std::vector<double> w;  // host scratch: weights per energy bin
     host::WeightTable wpre; // weights of the next fixed step, filled while the GPU sweeps
     uint32_t qcap = 0xFFFFFFFFu;  // tie-queue limit of the LDS-path sweeps (test hook)
+    int32_t stats_path = PA_STATS_AUTO;  // where the statistics of a swept population are taken
 };
 
 namespace {
@@ -172,6 +173,22 @@ void key_of(const pa_run* r, uint32_t* k0, uint32_t* k1, uint32_t* tag)
     *tag = r->p.run_id << 4;
 }
 
+// Whether the sweeps of this run take the statistics of the population they
+// make in their epilogue (else a separate pass, stats_kernel, takes them).
+// Measured per temperature step at theta = 1 (where the difference shows most),
+// against the separate pass: faster with one replica per wave up to about
+// 32768 replicas (L = 64: 1.6 us less at R = 20000; L = 128 within 1 us up to
+// R = 30000) and at L = 256 at every R (15-100 us less); slower beyond (L =
+// 128, R = 100000: 13 us more) and when a wave holds several replicas (L = 16,
+// 32: 2-13 us more), where the epilogue's reductions cost as much as a short
+// sweep.
+bool stats_in_epilogue(const pa_run* r)
+{
+    if (r->p.layout == PA_SPIN_INTERLEAVED) return false;
+    if (r->stats_path != PA_STATS_AUTO) return r->stats_path == PA_STATS_EPILOGUE;
+    return r->L == 256 || (r->L >= 64 && r->p.R <= 32768);
+}
+
 // The sweep kernel of the run's spin store: bit-sliced (int8 and bit stores)
 // or replica-parallel (interleaved store).
 hipError_t launch_sweep_of(const pa_run* r, pa::SweepArgs& a)
@@ -184,10 +201,10 @@ hipError_t launch_sweep_of(const pa_run* r, pa::SweepArgs& a)
 }
 
 // Queues nsweeps sweeps of the current population (or, with `init`, the
-// initial state; with neither, the recount of E and M).  On the bit-sliced
-// stores the sweep takes the population's statistics in its epilogue and the
-// gather publishes them to hstats, so the statistics of population version
-// `ver` need no separate pass (refresh_stats).
+// initial state; with neither, the recount of E and M).  Where the run takes
+// statistics in the epilogue (stats_in_epilogue), the gather publishes those
+// of population version `ver` to hstats, so they need no separate pass
+// (refresh_stats).
 pa_status launch_sweeps(pa_run* r, int32_t nsweeps, bool init, uint64_t ver)
 {
     pa::SweepArgs a;
@@ -203,7 +220,7 @@ pa_status launch_sweeps(pa_run* r, int32_t nsweeps, bool init, uint64_t ver)
     host::sweep_thresholds(hb, r->beta, &a.t2h, &a.t2l, &a.t4h, &a.t4l);
     a.init = init ? 1 : 0;
     a.qcap = r->qcap;
-    const bool epilogue = r->p.layout != PA_SPIN_INTERLEAVED;
+    const bool epilogue = stats_in_epilogue(r);
     if (epilogue) {
         a.acc = r->acc;
         a.acc_hist = r->acc_hist;
@@ -524,6 +541,7 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
         // replica-parallel sweep of the interleaved store works in place and
         // takes the copy first)
         const bool gather = sc->theta > 0 && r->p.layout != PA_SPIN_INTERLEAVED;
+        const bool epilogue = sc->theta > 0 && stats_in_epilogue(r);
         st = queue_resample(r, bn, !gather, &lnQ, &Emin, run_scratch(r));
         if (st != PA_OK) return st;
         const int nxt = r->cur ^ 1;
@@ -544,7 +562,7 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
             a.key1 = k1;
             a.tag = tag;
             a.qcap = r->qcap;
-            if (gather) {  // the statistics of the new population in the sweep's epilogue
+            if (epilogue) {  // the statistics of the new population in the sweep's epilogue
                 a.acc = r->acc;
                 a.acc_hist = r->acc_hist;
                 a.nbins = r->nbins;
@@ -560,7 +578,7 @@ pa_status pa_anneal(pa_run* r, const pa_schedule* sc, int32_t max_steps, pa_obs*
         // published to hstats, which then no longer holds those of the current
         // population, even if this step is refused
         r->gathered_version = 0;
-        if (gather)
+        if (epilogue)
             HIPCHK(pa::launch_stats_gather(r->acc, r->acc_hist, r->nbins, r->N, r->stats, r->hist, r->hstats_dev,
                                            r->stream));
         else
@@ -677,6 +695,15 @@ pa_status pa_set_tie_queue_cap(pa_run* r, int32_t cap)
     if (st != PA_OK) return st;
     if (cap < 0) return PA_EINVAL;
     r->qcap = (uint32_t)cap;
+    return PA_OK;
+}
+
+pa_status pa_set_stats_path(pa_run* r, int32_t mode)
+{
+    pa_status st = usable(r);
+    if (st != PA_OK) return st;
+    if (mode != PA_STATS_AUTO && mode != PA_STATS_EPILOGUE && mode != PA_STATS_PASS) return PA_EINVAL;
+    r->stats_path = mode;
     return PA_OK;
 }
 

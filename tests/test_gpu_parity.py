@@ -208,21 +208,24 @@ def test_statistics_windows_and_multi_histogram(L, R, kind, layout):
             assert _close(go[k], oo[k], 1e-12), (k, go["beta"], go[k], oo[k])
 
 
+@pytest.mark.parametrize("path", ["epilogue", "auto"])
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("L,R,kind", [(16, 3000, "mixed"), (64, 700, "ordered"), (64, 700, "mixed"),
                                       (128, 130, "mixed"), (256, 20, "mixed")])
-def test_statistics_from_the_sweep_epilogue_single_calls(L, R, kind, layout):
+def test_statistics_from_the_sweep_epilogue_single_calls(L, R, kind, layout, path):
     """Without the multi-histogram record, the statistics of a population made
     by a sweep (or by the recount after an upload) come from the sweep's
     epilogue and its gather; after a resampling with no sweep, from the
     statistics kernel.  Ordered and mixed populations give narrow and very
     wide energy windows; every measurement matches the oracle."""
-    print("case epilogue stats single calls L=%d R=%d %s layout=%s" % (L, R, kind, layout), flush=True)
+    print("case epilogue stats single calls L=%d R=%d %s layout=%s path=%s" % (L, R, kind, layout, path),
+          flush=True)
     if kind == "ordered":
         spins = inputs.ordered_spins(R, L, seed=41, n_flipped_max=40)
     else:
         spins = inputs.mixed_spins(R, L, seed=42)
     g = pa.Run(L, R, seed=23, layout=layout)
+    g.set_stats_path(path)
     o = oracle.Run(L, R, seed=23)
     g.upload_population(spins, step=1, sweeps=3, beta=0.3, lnZ=2.0)
     o.set_population(spins, step=1, sweeps=3, beta=0.3, lnZ=2.0)
@@ -354,17 +357,20 @@ def _fixed_betas(step0, beta0, beta_f, dbeta):
     return out
 
 
+@pytest.mark.parametrize("path", ["epilogue", "pass"])
 @pytest.mark.parametrize("layout", LAYOUTS)
 @pytest.mark.parametrize("L,R", [(16, 900), (32, 333), (64, 130), (128, 21), (256, 5)])
-def test_anneal_statistics_from_the_sweep_epilogue(L, R, layout):
+def test_anneal_statistics_from_the_sweep_epilogue(L, R, layout, path):
     """pa_anneal takes each step's statistics in the sweep's epilogue (per-wave
     atomics into accumulator slots and histogram copies, summed by a gather
-    pass that clears them again): every step's sums against the oracle at every
-    lattice size, with partial last waves at L = 16 and 32, over two calls on
-    one run, so leftovers of a step or of a call would show."""
-    print("case anneal epilogue statistics L=%d R=%d layout=%s" % (L, R, layout), flush=True)
+    pass that clears them again) or in a separate pass, each forced here at
+    every lattice size: every step's sums against the oracle, with partial last
+    waves at L = 16 and 32, over two calls on one run, so leftovers of a step
+    or of a call would show."""
+    print("case anneal statistics L=%d R=%d layout=%s path=%s" % (L, R, layout, path), flush=True)
     theta = 2
     g = pa.Run(L, R, seed=13, layout=layout)
+    g.set_stats_path(path)
     o = oracle.Run(L, R, seed=13)
     o.init()
     _same_obs(g.observables(), o.measure())
@@ -379,15 +385,20 @@ def test_anneal_statistics_from_the_sweep_epilogue(L, R, layout):
     _same_population(g, o)
 
 
+@pytest.mark.parametrize("path", ["epilogue", "pass"])
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_anneal_refusal_in_the_middle_of_a_run(layout):
+def test_anneal_refusal_in_the_middle_of_a_run(layout, path):
     """A step refused for capacity after other steps of the same pa_anneal
     call leaves the run at the last completed step, equal to the oracle's;
-    runs that are not refused match the oracle at every step."""
-    print("case anneal refusal mid-run layout=%s" % layout, flush=True)
+    runs that are not refused match the oracle at every step.  With the
+    statistics in the sweep's epilogue, the refused step has published the
+    refused population's statistics, which the run must not take for those
+    of its current one."""
+    print("case anneal refusal mid-run layout=%s path=%s" % (layout, path), flush=True)
     refused_late = 0
     for seed in range(1, 31):
         g = pa.Run(16, 100, seed=seed, capacity=100, layout=layout)
+        g.set_stats_path(path)
         o = oracle.Run(16, 100, seed=seed, capacity=100)
         s = np.ones((3, 16, 16), np.int8)
         g.upload_population(s, step=1, beta=0.1)
@@ -604,16 +615,27 @@ def test_capacity_overflow_and_extinction(layout):
     assert any(ext) and not all(ext)
 
 
+def test_stats_path_hook_rejects_unknown_modes():
+    g = pa.Run(16, 10, seed=1)
+    for bad in (-1, 3):
+        with pytest.raises(pa.PaError):
+            g.set_stats_path(bad)
+    for mode in ("auto", "epilogue", "pass"):
+        g.set_stats_path(mode)
+
+
+@pytest.mark.parametrize("path", ["epilogue", "pass"])
 @pytest.mark.parametrize("layout", LAYOUTS)
-def test_anneal_extinction_keeps_state(layout):
+def test_anneal_extinction_keeps_state(layout, path):
     """A pa_anneal step that would leave no replica (R = 1 from two equal
     replicas dies with probability 1/4) sweeps an empty population, whose
     statistics are empty: the call raises, the run stays at its last step
     with the oracle's population and statistics, and carries on."""
-    print("case anneal extinction layout=%s" % layout, flush=True)
+    print("case anneal extinction layout=%s path=%s" % (layout, path), flush=True)
     ext = []
     for seed in range(1, 25):
         g = pa.Run(16, 1, seed=seed, capacity=8, layout=layout)
+        g.set_stats_path(path)
         o = oracle.Run(16, 1, seed=seed, capacity=8)
         s = np.ones((2, 16, 16), np.int8)
         g.upload_population(s, step=1, beta=0.1)
