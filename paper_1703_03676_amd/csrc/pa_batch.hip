@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void b_scatter(const Item* __restrict__ ite
     const uint32_t c = (j < st.n_parent) ? rd.counts[j] : 0u;
     uint32_t total;
     const uint32_t off = rd.bsum[it.blk] + block_exclusive_scan(c, &total);
-    for (uint32_t k = 0; k < c; ++k) rd.parent[off + k] = (uint32_t)j;
+    fill_parents(rd.parent, off, c, (uint32_t)j - (threadIdx.x & 63u), 0xFFFFFFFFu);
 }
 
 // Item blk covers 16-byte chunks [blk * kBlock, (blk + 1) * kBlock) of the run's new population.

@@ -253,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void scatter_kernel(const uint32_t* __restr
     const uint32_t c = (j < n) ? counts[j] : 0u;
     uint32_t total;
     const uint32_t off = base + block_exclusive_scan(c, &total);
-    for (uint32_t k = 0; k < c && off + k < cap; ++k) parent[off + k] = (uint32_t)j;
+    fill_parents(parent, off, c, (uint32_t)(j - lane), cap);
     if (threadIdx.x == 0) {
         if (!scanned && blockIdx.x == gridDim.x - 1) st->r_new = base + total;
         if (blockIdx.x == 0) {

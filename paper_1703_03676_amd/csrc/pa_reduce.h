@@ -45,7 +45,33 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x, uint32_t* t
     return before + incl - x;
 }
 
-// Population statistics, first pass, for the replicas [i0, i0 + kBlock) of
+// Parent index of every child of one wave: lane L (parent first + L) owns the
+// children [off_L, off_L + c_L), and the lanes' ranges follow each other (an
+// exclusive scan of the counts).  The wave takes its children 64 at a time;
+// each lane finds the owner of its child by a binary search over the lanes'
+// range ends, so the cost follows the wave's number of children and not its
+// largest count (a parent with many copies no longer holds up the wave).
+// Children at or beyond cap are not written.  Called by every lane.
+__device__ __forceinline__ void fill_parents(uint32_t* __restrict__ parent, uint32_t off, uint32_t c,
+                                             uint32_t first, uint32_t cap)
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    const uint32_t end = off + c;
+    const uint32_t w0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)off);
+    const uint32_t w1 = (uint32_t)__builtin_amdgcn_readlane((int)end, 63);
+    for (uint32_t base = w0; base < w1; base += 64u) {
+        const uint32_t q = base + (uint32_t)lane;
+        int owner = 0;  // number of lanes whose range ends at or before q
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+            const uint32_t e = (uint32_t)__shfl((int)end, owner + step - 1);
+            if (e <= q) owner += step;
+        }
+        if (q < w1 && q < cap) parent[q] = first + (uint32_t)owner;
+    }
+}
+
+// Population statistics, first pass, for the replicas [i0, i0 + kBlock) of// Population statistics, first pass, for the replicas [i0, i0 + kBlock) of
 // one block (i < n only): the energy histogram n(b), b = (E + 2N) / 4, and, if
 // `record`, the per-energy accumulators of multi-histogram reweighting are
 // added to the population's arrays; the energy range and the exact sums of E,
