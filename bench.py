@@ -607,7 +607,9 @@ def main():
         cal.close()
     head = res[layouts[0]]
     achieved = head["sweep_flips_avg"] * SLOTS_PER_FLIP / (head["sweep_ms_avg"] * 1e-3)
-    traffic, valu_per_word = measured_counters() if args.update == "metropolis" else (None, None)
+    # the committed counter profile is of the Metropolis sweep on the bit store
+    profiled = args.update == "metropolis" and layouts[0] == "bits"
+    traffic, valu_per_word = measured_counters() if profiled else (None, None)
     # algorithmic HBM bytes of one sweep launch: every replica's spins read and
     # written once for all theta sweeps (N/8 or N bytes each way) plus E and M
     rep_bytes = L * L // 8 if layouts[0] == "bits" else L * L

@@ -193,11 +193,22 @@ __global__ __launch_bounds__(kBlock) void rp_sweep_kernel(SweepArgs a)
                     const U4 P = philox10((uint32_t)v, g, (uint32_t)j, a.tag | kStreamLcgSeed, a.key0, a.key1);
                     seeds = c == 0 ? P.x : P.y;
                 }
+                // The word's 32 spins and local fields are all read before any
+                // of its sites is updated: the neighbours of a site are of the
+                // other colour, which this half sweep does not change, so the
+                // result is the one of the site-by-site order, and the loads
+                // are in flight together instead of one site at a time.
+                int si[32], k[32];
+#pragma unroll
                 for (int b = 0; b < 32; ++b) {
                     const int s = Model::site(c, 32 * v + b);
-                    const int si = sp[(size_t)s * stride];
-                    const int k = si * Model::field(sp, stride, s);
-                    const uint64_t T = flip_threshold<HB>(k, T2, T4);
+                    si[b] = sp[(size_t)s * stride];
+                    k[b] = Model::field(sp, stride, s);
+                }
+#pragma unroll
+                for (int b = 0; b < 32; ++b) {
+                    const int kb = si[b] * k[b];
+                    const uint64_t T = flip_threshold<HB>(kb, T2, T4);
                     bool flip;
                     if constexpr (LCG) {
                         flip = T >= ((uint64_t)1 << 32) || (uint64_t)lcg_uniform(seeds, (uint32_t)b) < T;
@@ -205,9 +216,9 @@ __global__ __launch_bounds__(kBlock) void rp_sweep_kernel(SweepArgs a)
                         flip = wu.below((uint32_t)b, T);
                     }
                     if (flip) {
-                        sp[(size_t)s * stride] = (int8_t)-si;
-                        E += 2 * k;
-                        M -= 2 * si;
+                        sp[(size_t)Model::site(c, 32 * v + b) * stride] = (int8_t)-si[b];
+                        E += 2 * kb;
+                        M -= 2 * si[b];
                     }
                 }
             }
