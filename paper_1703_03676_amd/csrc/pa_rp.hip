@@ -148,39 +148,62 @@ __device__ __forceinline__ void recount(const int8_t* sp, size_t stride, int32_t
     *M = m;
 }
 
+// Lanes per replica: from L = 64 on, the words of one colour are shared out
+// among four lanes of one wave (lane = part * 16 + r holds replica 16 w + r of
+// wave w), so a launch has four times as many threads as replicas; within a
+// half sweep the parts' sites do not neighbour each other, and the block waits
+// for all of them before the other colour.  Below, one lane per replica (the
+// kernels then need more registers per lane than four parts leave).
+template <int L>
+struct RpShape {
+    static constexpr int PARTS = L >= 64 ? 4 : 1;
+    static constexpr int REPS_PER_WAVE = 64 / PARTS;
+    static constexpr int REPS_PER_BLOCK = (kBlock / 64) * REPS_PER_WAVE;
+    static constexpr int BATCH = L >= 64 ? 16 : 32;  // sites whose spins and fields are read together
+};
+
 template <int L, int U>
 __global__ __launch_bounds__(kBlock) void rp_sweep_kernel(SweepArgs a)
 {
     using Model = Ising2D<L>;
+    using Sh = RpShape<L>;
     constexpr bool HB = U == kHeatbath, LCG = U == kLcg;
+    constexpr int WORDS = Model::HALF / 32;  // 32-site words per colour
+    constexpr int kRpParts = Sh::PARTS, kRpRepsPerWave = Sh::REPS_PER_WAVE, kRpBatch = Sh::BATCH;
     int32_t n = a.n_rep;
     if (a.n_dev) n = min(n, (int32_t)*a.n_dev);
-    const int j = (int)(blockIdx.x * kBlock + threadIdx.x);
-    if (j >= n) return;
+    const int lane = (int)(threadIdx.x & 63u), part = lane / kRpRepsPerWave;
+    const int j = (int)(blockIdx.x * Sh::REPS_PER_BLOCK + (threadIdx.x >> 6) * kRpRepsPerWave) +
+                  (lane & (kRpRepsPerWave - 1));
+    const bool valid = j < n;
     const size_t stride = a.stride;
     int8_t* sp = reinterpret_cast<int8_t*>(a.spin) + j;
-    if (a.init) {
-        // initial state: INIT output word p >> 5 (p = c N/2 + q), bit p & 31 set = spin -1
-        for (int pb = 0; pb < Model::N / 128; ++pb) {
-            const U4 P = philox10((uint32_t)pb, 0u, (uint32_t)j, a.tag | kStreamInit, a.key0, a.key1);
-            const uint32_t w[4] = {P.x, P.y, P.z, P.w};
-            for (int k = 0; k < 128; ++k) {
-                const int p = pb * 128 + k, c = p / Model::HALF, q = p - c * Model::HALF;
-                sp[(size_t)Model::site(c, q) * stride] = ((w[k >> 5] >> (k & 31)) & 1u) ? (int8_t)-1 : (int8_t)1;
+    if (a.init || a.nsweeps == 0) {  // initial state or recount: one lane per replica
+        if (!valid || part != 0) return;
+        if (a.init) {
+            // initial state: INIT output word p >> 5 (p = c N/2 + q), bit p & 31 set = spin -1
+            for (int pb = 0; pb < Model::N / 128; ++pb) {
+                const U4 P = philox10((uint32_t)pb, 0u, (uint32_t)j, a.tag | kStreamInit, a.key0, a.key1);
+                const uint32_t w[4] = {P.x, P.y, P.z, P.w};
+                for (int k = 0; k < 128; ++k) {
+                    const int p = pb * 128 + k, c = p / Model::HALF, q = p - c * Model::HALF;
+                    sp[(size_t)Model::site(c, q) * stride] = ((w[k >> 5] >> (k & 31)) & 1u) ? (int8_t)-1 : (int8_t)1;
+                }
             }
         }
-    }
-    if (a.init || a.nsweeps == 0) {
         recount<L>(sp, stride, &a.E[j], &a.M[j]);
         return;
     }
-    int32_t E = a.E[j], M = a.M[j];
+    // every lane of the block takes part in the barriers; lanes beyond the
+    // population do no work
+    int32_t dE = 0, dM = 0;
     const uint64_t T2 = ((uint64_t)a.t2h << 16) + a.t2l, T4 = ((uint64_t)a.t4h << 16) + a.t4l;
     for (int t = 0; t < a.nsweeps; ++t) {
         const uint32_t g = a.g0 + (uint32_t)t;
-        uint32_t seeds = 0;  // LCG: the seed of the current word and colour
+#pragma unroll 1
         for (int c = 0; c < 2; ++c) {
-            for (int v = 0; v < Model::HALF / 32; ++v) {
+#pragma unroll 1
+            for (int v = part; valid && v < WORDS; v += kRpParts) {
                 WordUniform wu;
                 wu.v = (uint32_t)v;
                 wu.ctr1 = 2u * g + (uint32_t)c;
@@ -189,43 +212,57 @@ __global__ __launch_bounds__(kBlock) void rp_sweep_kernel(SweepArgs a)
                 wu.key0 = a.key0;
                 wu.key1 = a.key1;
                 wu.have = 0;
+                uint32_t seed = 0;  // LCG: the seed of this word and colour
                 if constexpr (LCG) {
                     const U4 P = philox10((uint32_t)v, g, (uint32_t)j, a.tag | kStreamLcgSeed, a.key0, a.key1);
-                    seeds = c == 0 ? P.x : P.y;
+                    seed = c == 0 ? P.x : P.y;
                 }
-                // The word's 32 spins and local fields are all read before any
-                // of its sites is updated: the neighbours of a site are of the
-                // other colour, which this half sweep does not change, so the
-                // result is the one of the site-by-site order, and the loads
-                // are in flight together instead of one site at a time.
-                int si[32], k[32];
+                // The spins and local fields of kRpBatch sites are all read
+                // before any of them is updated: the neighbours of a site are
+                // of the other colour, which this half sweep does not change,
+                // so the result is the one of the site-by-site order, and the
+                // loads are in flight together instead of one site at a time.
 #pragma unroll
-                for (int b = 0; b < 32; ++b) {
-                    const int s = Model::site(c, 32 * v + b);
-                    si[b] = sp[(size_t)s * stride];
-                    k[b] = Model::field(sp, stride, s);
+                for (int b0 = 0; b0 < 32; b0 += kRpBatch) {
+                int si[kRpBatch], k[kRpBatch];
+#pragma unroll
+                for (int i = 0; i < kRpBatch; ++i) {
+                    const int s = Model::site(c, 32 * v + b0 + i);
+                    si[i] = sp[(size_t)s * stride];
+                    k[i] = Model::field(sp, stride, s);
                 }
 #pragma unroll
-                for (int b = 0; b < 32; ++b) {
-                    const int kb = si[b] * k[b];
+                for (int i = 0; i < kRpBatch; ++i) {
+                    const int b = b0 + i;
+                    const int kb = si[i] * k[i];
                     const uint64_t T = flip_threshold<HB>(kb, T2, T4);
                     bool flip;
                     if constexpr (LCG) {
-                        flip = T >= ((uint64_t)1 << 32) || (uint64_t)lcg_uniform(seeds, (uint32_t)b) < T;
+                        flip = T >= ((uint64_t)1 << 32) || (uint64_t)lcg_uniform(seed, (uint32_t)b) < T;
                     } else {
                         flip = wu.below((uint32_t)b, T);
                     }
                     if (flip) {
-                        sp[(size_t)Model::site(c, 32 * v + b) * stride] = (int8_t)-si[b];
-                        E += 2 * kb;
-                        M -= 2 * si[b];
+                        sp[(size_t)Model::site(c, 32 * v + b) * stride] = (int8_t)-si[i];
+                        dE += 2 * kb;
+                        dM -= 2 * si[i];
                     }
                 }
+                }
             }
+            if constexpr (kRpParts > 1) __syncthreads();  // this colour's updates, before the other colour reads them
         }
     }
-    a.E[j] = E;
-    a.M[j] = M;
+    // the parts' energy and magnetisation changes, summed over the replica's lanes
+#pragma unroll
+    for (int off = kRpRepsPerWave; off < 64; off <<= 1) {
+        dE += __shfl_xor(dE, off);
+        dM += __shfl_xor(dM, off);
+    }
+    if (valid && part == 0) {
+        a.E[j] += dE;
+        a.M[j] += dM;
+    }
 }
 
 // Replica copy child <- parent[child] of the interleaved store, for child <
@@ -256,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void rp_copy_kernel(const int8_t* __restric
 template <int L, int U>
 hipError_t launch_rp_t(const SweepArgs& a, hipStream_t s)
 {
-    const int blocks = (a.n_rep + kBlock - 1) / kBlock;
+    const int blocks = (a.n_rep + RpShape<L>::REPS_PER_BLOCK - 1) / RpShape<L>::REPS_PER_BLOCK;
     if (blocks == 0) return hipSuccess;
     hipLaunchKernelGGL((rp_sweep_kernel<L, U>), dim3(blocks), dim3(kBlock), 0, s, a);
     return hipGetLastError();
