@@ -1,11 +1,12 @@
 // Replica-parallel kernels for the interleaved spin store (PA_SPIN_INTERLEAVED):
-// one thread per replica goes through its whole lattice, site by site (Sec. 3,
-// spin updates: the replica-parallel setup, with the same spin of all replicas
-// next to each other in memory so that the threads of a wave read and write
-// adjacent bytes).  The scheme needs nothing of the model but a site's
-// neighbours and the energy change of its update, so it serves as the general
-// fall-back the paper describes; its parallelism is one thread per replica,
-// too little to fill the GPU for small populations.
+// each replica is swept by its own thread, site by site (Sec. 3, spin updates:
+// the replica-parallel setup, with the same spin of all replicas next to each
+// other in memory so that the threads of a wave read and write adjacent bytes);
+// from L = 64 on, four lanes share a replica's sites of one colour.  The scheme
+// needs nothing of the model but a site's neighbours and the energy change of
+// its update, so it serves as the general fall-back the paper describes; its
+// parallelism is a few threads per replica, too little to fill the GPU for
+// small populations.
 //
 // Store: spin (x, y) of replica j is the signed byte at (y L + x) * stride + j,
 // stride = the capacity rounded up to 64.
