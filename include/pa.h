@@ -59,8 +59,9 @@ typedef enum {
     PA_SPIN_BITS = 1,   /* one bit per spin, per-colour 32-site words (multi-spin coding) */
     PA_SPIN_INTERLEAVED = 2  /* one signed byte per spin, the same spin of all replicas adjacent
                                 (spin (x, y) of replica j at byte (y L + x) * stride + j, stride the
-                                capacity rounded up to 64), swept replica-parallel: one thread per
-                                replica goes through its lattice site by site (Sec. 3, the
+                                capacity rounded up to 64), swept replica-parallel: each replica
+                                goes through its lattice site by site on its own thread (four lanes
+                                sharing a colour's sites from L = 64 on; Sec. 3, the
                                 replica-parallel setup, the paper's general fall-back); single runs
                                 only (pa_batch_init refuses it) */
 } pa_layout;
