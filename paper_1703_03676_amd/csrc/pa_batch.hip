@@ -642,8 +642,10 @@ struct pa_batch {
     std::vector<Group> groups;
     uint8_t* h_steps = nullptr;     // pinned: step descriptors + tables
     uint8_t* h_download = nullptr;  // pinned: results + statistics
-    hipGraph_t graph = nullptr;
+    hipGraph_t graph = nullptr;        // one step, with the separate replica copy (b_copy)
     hipGraphExec_t exec = nullptr;
+    hipGraph_t graph_nocopy = nullptr; // the same step without it: every resampled run sweeps and
+    hipGraphExec_t exec_nocopy = nullptr;  // so gathers its parents in b_sweep (the usual case)
     pa::batch::Pool* pool = nullptr;
     pa_batch_options opt{0};  // forced launch shape (0: autotuned)
     bool broken = false;
@@ -748,8 +750,9 @@ std::vector<Item> sweep_items(const pa_batch* b, const Group& g, int wpb)
     return it;
 }
 
-// Enqueue the device part of one step (captured into the graph).
-pa_status enqueue_step(pa_batch* b)
+// Enqueue the device part of one step (captured into the graphs), with or
+// without the separate replica copy of runs that resample without sweeping.
+pa_status enqueue_step(pa_batch* b, bool with_copy)
 {
     const hipStream_t s = b->stream;
     const Item* items = b->d_items;
@@ -763,7 +766,7 @@ pa_status enqueue_step(pa_batch* b)
     hipLaunchKernelGGL(b_scatter, dim3((unsigned)b->n_parent_items), dim3(kBlock), 0, s, items + b->parent_off,
                        b->d_rundev, b->d_steps, b->d_results);
     BCHK(hipGetLastError());
-    if (b->n_copy_items) {
+    if (with_copy && b->n_copy_items) {
         hipLaunchKernelGGL(b_copy, dim3((unsigned)b->n_copy_items), dim3(kBlock), 0, s, items + b->copy_off,
                            b->d_rundev, b->d_steps, b->d_results);
         BCHK(hipGetLastError());
@@ -791,12 +794,15 @@ uint32_t* host_tables(pa_batch* b)
     return reinterpret_cast<uint32_t*>(b->h_steps + (b->lo.tables - b->lo.steps));
 }
 
-// Runs one replay of the step graph after uploading the first `bytes` bytes
-// of the step descriptors and packed tables.
-pa_status replay(pa_batch* b, size_t bytes)
+// Runs one replay of a step graph after uploading the first `bytes` bytes of
+// the step descriptors and packed tables: the one with the separate replica
+// copy only if some run resamples without sweeping (its b_copy launch covers
+// every run's capacity and costs tens of microseconds even when it has
+// nothing to do).
+pa_status replay(pa_batch* b, size_t bytes, bool need_copy)
 {
     BCHK(hipMemcpyAsync(b->d_steps, b->h_steps, bytes, hipMemcpyHostToDevice, b->stream));
-    BCHK(hipGraphLaunch(b->exec, b->stream));
+    BCHK(hipGraphLaunch(need_copy ? b->exec : b->exec_nocopy, b->stream));
     BCHK(hipStreamSynchronize(b->stream));
     return PA_OK;
 }
@@ -1052,15 +1058,17 @@ static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int
         g.n_items = it.size();
     }
     BCHK(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(Item), hipMemcpyHostToDevice, b->stream));
-    // capture one step
-    BCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    st = enqueue_step(b);
-    hipGraph_t g = nullptr;
-    const hipError_t ce = hipStreamEndCapture(b->stream, &g);
-    if (st != PA_OK) return st;
-    BCHK(ce);
-    b->graph = g;
-    BCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    // capture one step, with and without the separate replica copy
+    for (int with_copy = 1; with_copy >= 0; --with_copy) {
+        BCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+        st = enqueue_step(b, with_copy != 0);
+        hipGraph_t g = nullptr;
+        const hipError_t ce = hipStreamEndCapture(b->stream, &g);
+        if (st != PA_OK) return st;
+        BCHK(ce);
+        (with_copy ? b->graph : b->graph_nocopy) = g;
+        BCHK(hipGraphInstantiate(with_copy ? &b->exec : &b->exec_nocopy, g, nullptr, nullptr, 0));
+    }
     // initial state (Sec. 2.1 step 1) and the measurement at beta_0 = 0
     StepDev* sd = host_steps(b);
     for (int r = 0; r < nruns; ++r) {
@@ -1075,7 +1083,7 @@ static pa_status batch_init(const pa_params* runs, const pa_schedule* sched, int
         h.R_cur = h.p.R;
         h.lnZ = (double)(h.p.L * h.p.L) * std::log(2.0);
     }
-    st = replay(b, b->lo.tables - b->lo.steps);
+    st = replay(b, b->lo.tables - b->lo.steps, false);  // initial states: no resampling
     if (st != PA_OK) return st;
     for (int r = 0; r < nruns; ++r) {
         read_stats(b, r);
@@ -1153,7 +1161,10 @@ pa_status pa_batch_step(pa_batch* b, int32_t* n_active)
         d.last_dbeta = bn - h.beta;
     });
     if (any) {
-        const pa_status st = replay(b, (b->lo.tables - b->lo.steps) + (size_t)o * 4);
+        bool need_copy = false;
+        for (int r = 0; r < b->nruns; ++r)
+            need_copy = need_copy || (sd[r].active && sd[r].resample && sd[r].nsweeps == 0);
+        const pa_status st = replay(b, (b->lo.tables - b->lo.steps) + (size_t)o * 4, need_copy);
         if (st != PA_OK) return st;
         const ResultDev* res = reinterpret_cast<const ResultDev*>(b->h_download);
         b->pool->parallel_for(b->nruns, [&](int r) {
@@ -1350,6 +1361,8 @@ pa_status pa_batch_free(pa_batch* b)
     if (!b) return PA_OK;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->exec_nocopy) (void)hipGraphExecDestroy(b->exec_nocopy);
+    if (b->graph_nocopy) (void)hipGraphDestroy(b->graph_nocopy);
     if (b->h_steps) (void)hipHostFree(b->h_steps);
     if (b->h_download) (void)hipHostFree(b->h_download);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);

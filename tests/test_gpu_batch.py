@@ -116,6 +116,35 @@ def test_mixed_batch_matches_independent_oracle_runs(wpb, qcap):
                     assert _close(go[k], oo[k]), (k, go[k], oo[k])
 
 
+def test_batch_with_resampling_only_runs():
+    """Runs with theta = 0 resample without sweeping, so they need the separate
+    replica copy, whose step graph the batch replays only in steps where such
+    a run resamples; here mixed with sweeping runs in the same steps (and the
+    sweeping runs go on alone after the others have finished)."""
+    print("case batch with theta = 0 runs", flush=True)
+    runs = [dict(L=16, R=300, seed=31, layout="bits"), dict(L=64, R=40, seed=32, layout="int8"),
+            dict(L=128, R=6, seed=33, layout="bits"), dict(L=32, R=150, seed=34, layout="int8"),
+            dict(L=256, R=3, seed=35, layout="bits")]
+    scheds = [dict(beta_f=0.6, dbeta=0.1, theta=0, mode="fixed"),
+              dict(beta_f=0.6, dbeta=0.1, theta=2, mode="fixed"),
+              dict(beta_f=0.4, dbeta=0.1, theta=0, mode="fixed"),
+              dict(beta_f=0.9, alpha_star=0.85, theta=0, mode="adaptive"),
+              dict(beta_f=0.8, dbeta=0.1, theta=1, mode="fixed")]
+    b = pa.Batch(runs, scheds)
+    b.run()
+    for r, (spec, sc) in enumerate(zip(runs, scheds)):
+        print("  run %d L=%d theta=%d" % (r, spec["L"], sc["theta"]), flush=True)
+        assert b.status(r) == pa.PA_OK
+        o, trace = _oracle_trace(spec, sc)
+        hist = b.history(r)
+        assert len(hist) == len(trace)
+        for go, oo in zip(hist, trace):
+            _same_obs(go, oo)
+        gs, gE, gM = b.download_population(r)
+        os_, oE, oM = o.get_population()
+        assert np.array_equal(gE, oE) and np.array_equal(gM, oM) and np.array_equal(gs, os_)
+
+
 def test_batch_equals_single_runs():
     # the same run alone through the single-run API
     print("case batch vs single", flush=True)
