@@ -26,6 +26,23 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(pa.SIGNATURES)
 
 
+def test_header_is_plain_c(tmp_path):
+    """include/pa.h is a C header of plain types: it compiles as C99 with gcc
+    -pedantic -Werror, and every declared entry point can be named from C."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    src = tmp_path / "uses_header.c"
+    refs = "\n".join("    (void)&%s;" % n for n in declared_functions())
+    src.write_text('#include "pa.h"\nint main(void)\n{\n%s\n    return 0;\n}\n' % refs)
+    r = subprocess.run([gcc, "-std=c99", "-pedantic", "-Wall", "-Wextra", "-Werror", "-I",
+                        os.path.join(ROOT, "include"), "-c", str(src), "-o", str(tmp_path / "uses_header.o")],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+
+
 def test_status_codes_match_header():
     txt = open(HEADER).read()
     for name, val in re.findall(r"(PA_E[A-Z]+|PA_OK)\s*=\s*(-?\d+)", txt):
