@@ -124,7 +124,7 @@ struct pa_run {
     std::vector<uint32_t> h_hist;
     uint8_t* pinned;
     size_t pinned_bytes;
-    uint32_t* hstats = nullptr;  // pinned: statistics block + histogram window, written by the statistics kernel
+    uint32_t* hstats = nullptr;  // pinned: statistics block + histogram window, written by the statistics kernel or gather
     void* hstats_dev = nullptr;  // device view of hstats
     hipEvent_t ev_rnew = nullptr;  // marks the resampling total in host memory
     hipEvent_t ev_t0 = nullptr, ev_t1 = nullptr;  // sweep timing in pa_anneal (created on first use)
@@ -237,8 +237,9 @@ pa_status launch_sweeps(pa_run* r, int32_t nsweeps, bool init, uint64_t ver)
 }
 
 // Reads the statistics block and the histogram window that the statistics
-// kernel wrote to pinned host memory (after the stream has been synchronised);
-// bins outside [emin, emax] of h_hist are not used.
+// kernel or the gather of a sweep's epilogue wrote to pinned host memory
+// (after the stream has been synchronised); bins outside [emin, emax] of
+// h_hist are not used.
 pa_status read_host_stats(pa_run* r, DevStats* out)
 {
     std::memcpy(out, r->hstats, sizeof(DevStats));
