@@ -50,6 +50,19 @@ def test_status_codes_match_header():
         assert pa.strerror(int(val)) != "unknown status"
 
 
+def test_header_constants_match_binding():
+    """Every enum value and macro the header defines with a plain number (layouts,
+    flags, step modes, statistics paths, limits) that the binding also names has
+    the same value there."""
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    consts = dict(re.findall(r"\b(PA_[A-Z_0-9]+)\s*=\s*(-?\d+)", txt))
+    consts.update(re.findall(r"#define\s+(PA_[A-Z_0-9]+)\s+\(?(\d+)\)?\s*$", txt, flags=re.M))
+    shared = [k for k in consts if hasattr(pa, k)]
+    assert {"PA_SPIN_INTERLEAVED", "PA_FLAG_LCG", "PA_STATS_PASS"} <= set(shared)
+    for k in shared:
+        assert getattr(pa, k) == int(consts[k]), k
+
+
 def test_workspace_bytes_validation():
     ok = pa.make_params(64, 20000, 1)
     n_bits = pa.workspace_bytes(ok)
@@ -102,6 +115,8 @@ def test_null_handle():
     assert lib.pa_resample(None, 0.1, None) == pa.PA_EINVAL
     assert lib.pa_observables(None, None) == pa.PA_EINVAL
     assert lib.pa_state(None, None) == pa.PA_EINVAL
+    assert lib.pa_set_tie_queue_cap(None, 8) == pa.PA_EINVAL
+    assert lib.pa_set_stats_path(None, pa.PA_STATS_EPILOGUE) == pa.PA_EINVAL
     sched = pa.make_schedule(beta_f=1.0, dbeta=0.01, theta=1)
     n = ctypes.c_int32(7)
     assert lib.pa_anneal(None, ctypes.byref(sched), 10, None, None, 0, ctypes.byref(n)) == pa.PA_EINVAL
